@@ -1,0 +1,361 @@
+"""Pins for the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against the definition of a maximal clique
+(Section 1), closed forms (Moon-Moser, complete multipartite, complete,
+edgeless, cycle), the paper's worked IMCE examples (Section 5), invariants of
+the decomposition (Algorithm 4: each clique is found by its lowest-rank
+vertex), textbook definitions of the rank metrics, and published splitmix64
+output values for the hash.
+"""
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RANKS = ("degree", "degeneracy", "triangle")
+
+
+# --------------------------------------------------------------------------
+# hash
+
+def test_mix64_matches_published_splitmix64_outputs():
+    # splitmix64 seeded with 0: first output 0xe220a8397b1dcdaf; seeded with
+    # 1234567: 6457827717110365317, 3203168211198807973, ... (published test
+    # vectors of the generator; the state advances by the golden gamma)
+    G = 0x9E3779B97F4A7C15
+    M = (1 << 64) - 1
+    assert O.mix64(0) == 0xE220A8397B1DCDAF
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    assert [O.mix64((1234567 + i * G) & M) for i in range(5)] == want
+
+
+def test_clique_hash_is_order_free_and_separates_small_families():
+    assert O.clique_hash([3, 1, 2]) == O.clique_hash([1, 2, 3])
+    seen = {}
+    for k in range(1, 4):
+        for c in itertools.combinations(range(12), k):
+            h = O.clique_hash(c)
+            assert h not in seen, (c, seen.get(h))
+            seen[h] = c
+
+
+# --------------------------------------------------------------------------
+# definition: brute force
+
+def _cliques_by_hand(n, edges):
+    adj = {v: set() for v in range(n)}
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    out = []
+    for k in range(1, n + 1):
+        for s in itertools.combinations(range(n), k):
+            if all(b in adj[a] for a, b in itertools.combinations(s, 2)):
+                if not any(all(w in adj[x] for x in s) for w in range(n) if w not in s):
+                    out.append(s)
+    return sorted(out)
+
+
+@pytest.mark.parametrize("n,edges,expect", [
+    (3, [(0, 1), (1, 2), (0, 2)], [(0, 1, 2)]),
+    (3, [(0, 1), (1, 2)], [(0, 1), (1, 2)]),
+    (4, [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3)], [(0, 1, 2), (0, 1, 3)]),
+    (3, [], [(0,), (1,), (2,)]),
+    (5, [(0, 1), (2, 3)], [(0, 1), (2, 3), (4,)]),
+])
+def test_brute_force_on_hand_checked_graphs(n, edges, expect):
+    g = gg.from_edge_list(n, edges)
+    cnt, h, cl = O.mce_brute(g, cliques=True)
+    assert cl == expect
+    assert cnt == len(expect)
+    assert h == sum(O.clique_hash(c) for c in expect) % (1 << 64)
+
+
+def test_brute_force_matches_python_definition():
+    rng = np.random.default_rng(7)
+    for t in range(40):
+        n = int(rng.integers(1, 9))
+        p = float(rng.random())
+        g = gg.er(n, p, seed=100 + t)
+        u, v = gg.edges_of(g)
+        assert O.mce_brute(g, cliques=True)[2] == _cliques_by_hand(n, list(zip(u.tolist(), v.tolist())))
+
+
+def test_empty_graph_has_no_cliques():
+    g = gg.edgeless(0)
+    assert O.mce_brute(g)[:2] == (0, 0)
+    assert O.mce_root(g)[:2] == (0, 0)
+    r = O.mce_parmce(g)
+    assert (r.count, r.set_hash) == (0, 0)
+
+
+def test_ttt_and_parmce_equal_brute_force_on_random_small_graphs():
+    rng = np.random.default_rng(11)
+    for t in range(400):
+        n = int(rng.integers(1, 19))
+        p = float(rng.choice([0.1, 0.3, 0.5, 0.7, 0.9, rng.random()]))
+        g = gg.er(n, p, seed=t)
+        cnt, h, cl = O.mce_brute(g, cliques=True)
+        c2, h2, _, cl2 = O.mce_root(g, cliques=True)
+        assert (c2, h2, cl2) == (cnt, h, cl)
+        for rk in RANKS:
+            r = O.mce_parmce(g, rk, cliques=True)
+            assert (r.count, r.set_hash) == (cnt, h)
+            assert r.cliques == cl
+
+
+# --------------------------------------------------------------------------
+# closed forms
+
+def _moon_moser_count(n):
+    if n % 3 == 0:
+        return 3 ** (n // 3)
+    if n % 3 == 1:
+        return 4 * 3 ** ((n - 4) // 3)
+    return 2 * 3 ** ((n - 2) // 3)
+
+
+@pytest.mark.parametrize("n", list(range(2, 31)) + [33, 36])
+def test_moon_moser_count(n):
+    g = gg.moon_moser(n)
+    want = _moon_moser_count(n) if n >= 4 or n % 3 != 1 else 1
+    assert O.mce_root(g)[0] == want
+    assert O.mce_parmce(g, "degree").count == want
+
+
+def test_complete_multipartite_cliques_are_the_transversals():
+    for sizes in ([1], [2, 3], [3, 1, 2], [4, 4, 1, 2], [5, 3, 2, 2]):
+        g = gg.complete_multipartite(sizes)
+        parts, off = [], 0
+        for s in sizes:
+            parts.append(list(range(off, off + s)))
+            off += s
+        transversals = sorted(tuple(sorted(t)) for t in itertools.product(*parts))
+        want_h = sum(O.clique_hash(t) for t in transversals) % (1 << 64)
+        c, h, _, cl = O.mce_root(g, cliques=True)
+        assert c == math.prod(sizes) and cl == transversals and h == want_h
+        for rk in RANKS:
+            r = O.mce_parmce(g, rk)
+            assert (r.count, r.set_hash) == (c, want_h)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 40, 100])
+def test_complete_graph_one_clique_and_node_count(n):
+    g = gg.complete(n)
+    r = O.mce_parmce(g, "degree")
+    assert r.count == 1 and r.set_hash == O.clique_hash(range(n))
+    # degree ranking on K_n: vertex 0 walks a chain of n nodes; every other
+    # vertex has a fini vertex adjacent to all of cand, so one node each.
+    assert r.nodes == 2 * n - 1
+
+
+@pytest.mark.parametrize("n", [1, 5, 64])
+def test_edgeless_graph_singletons(n):
+    g = gg.edgeless(n)
+    r = O.mce_parmce(g, "degree")
+    assert r.count == n and r.nodes == n
+    assert r.set_hash == sum(O.clique_hash([v]) for v in range(n)) % (1 << 64)
+
+
+@pytest.mark.parametrize("n", [4, 5, 9, 50])
+def test_cycle_cliques_are_its_edges(n):
+    g = gg.cycle(n)
+    c, h, _, cl = O.mce_root(g, cliques=True)
+    assert cl == sorted(tuple(sorted((i, (i + 1) % n))) for i in range(n))
+
+
+def test_disjoint_union_adds_and_relabelling_maps():
+    a = gg.er(14, 0.5, seed=3)
+    b = gg.er(11, 0.6, seed=4)
+    u = gg.disjoint_union(a, b)
+    ca, _, _, cla = O.mce_root(a, cliques=True)
+    cb, _, _, clb = O.mce_root(b, cliques=True)
+    cu, hu, _, clu = O.mce_root(u, cliques=True)
+    assert cu == ca + cb
+    assert clu == sorted(cla + [tuple(x + a.n for x in c) for c in clb])
+    perm = np.random.default_rng(5).permutation(u.n)
+    cr, _, _, clr = O.mce_root(gg.relabel(u, perm), cliques=True)
+    assert clr == sorted(tuple(sorted(int(perm[x]) for x in c)) for c in clu)
+
+
+def test_er_clique_count_near_expectation():
+    # E|C| for G(n,p) = sum_k C(n,k) p^C(k,2) (1-p^k)^(n-k)
+    n, p = 2000, 0.01
+    e = sum(math.comb(n, k) * p ** math.comb(k, 2) * (1 - p ** k) ** (n - k) for k in range(1, 8))
+    c = O.mce_root(gg.er(n, p, 0))[0]
+    assert abs(c - e) / e < 0.03
+
+
+# --------------------------------------------------------------------------
+# decomposition (Algorithm 4)
+
+def test_each_clique_is_found_by_its_lowest_rank_vertex():
+    for seed in range(6):
+        g = gg.er(40, 0.25, seed=seed)
+        cl = O.mce_root(g, cliques=True)[3]
+        for rk in RANKS:
+            m = O.rank_metric(g, rk)
+            r = O.mce_parmce(g, rk)
+            owners = np.zeros(g.n, dtype=np.int64)
+            for c in cl:
+                owners[min(c, key=lambda v: (int(m[v]), v))] += 1
+            assert np.array_equal(owners, r.count_v.astype(np.int64))
+            assert int(r.count_v.sum()) == len(cl)
+
+
+def test_subset_of_subproblems_matches_full_run():
+    g = gg.er(300, 0.05, seed=9)
+    full = O.mce_parmce(g, "degeneracy")
+    sel = np.array([5, 17, 100, 299, 3], dtype=np.uint32)
+    part = O.mce_parmce(g, "degeneracy", verts=sel)
+    assert np.array_equal(part.nodes_v, full.nodes_v[sel])
+    assert np.array_equal(part.count_v, full.count_v[sel])
+    assert np.array_equal(part.hash_v, full.hash_v[sel])
+
+
+def test_threads_do_not_change_results():
+    g = gg.rmat(9, seed=3)
+    a = O.mce_parmce(g, "degeneracy", threads=1)
+    b = O.mce_parmce(g, "degeneracy", threads=4)
+    assert (a.count, a.set_hash, a.nodes) == (b.count, b.set_hash, b.nodes)
+    assert np.array_equal(a.nodes_v, b.nodes_v)
+
+
+# --------------------------------------------------------------------------
+# rank metrics (Section 4.2)
+
+def _k_core_numbers(g):
+    n = g.n
+    adj = [set(g.neighbors(v).tolist()) for v in range(n)]
+    core = np.zeros(n, dtype=np.int64)
+    k = 0
+    alive = set(range(n))
+    while alive:
+        # the k-core: repeatedly delete vertices of degree < k
+        sub = set(alive)
+        changed = True
+        while changed:
+            changed = False
+            for v in list(sub):
+                if len(adj[v] & sub) < k:
+                    sub.discard(v)
+                    changed = True
+        for v in sub:
+            core[v] = k
+        alive = sub
+        k += 1
+    return core
+
+
+def test_rank_metrics_match_definitions():
+    for seed in range(4):
+        g = gg.er(60, 0.12, seed=seed)
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        assert np.array_equal(O.rank_metric(g, "degree").astype(np.int64), deg)
+        assert np.array_equal(O.rank_metric(g, "degeneracy").astype(np.int64), _k_core_numbers(g))
+        A = np.zeros((g.n, g.n), dtype=np.int64)
+        u, v = gg.edges_of(g)
+        A[u, v] = 1
+        A[v, u] = 1
+        tri = np.diag(A @ A @ A) // 2
+        assert np.array_equal(O.rank_metric(g, "triangle").astype(np.int64), tri)
+
+
+# --------------------------------------------------------------------------
+# IMCE (Section 5)
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _as_ids(fx, items):
+    if "vertices" in fx:
+        m = fx["vertices"]
+        return [tuple(sorted(m[x] for x in it)) for it in items]
+    return [tuple(sorted(it)) for it in items]
+
+
+@pytest.mark.parametrize("name", ["fig3_imce.json", "cut_figure_imce.json"])
+def test_imce_worked_examples(name):
+    fx = _load(name)
+    edges = _as_ids(fx, fx["edges"])
+    g = gg.from_edge_list(fx["n"], edges)
+    st = O.Imce(g)
+    c, h, cl = st.snapshot(cliques=True)
+    assert cl == sorted(_as_ids(fx, fx["initial_cliques"]))
+    for b in fx["batches"]:
+        add = _as_ids(fx, b["add"])
+        r = st.add([a for a, _ in add], [x for _, x in add], cliques=True, check_form=True)
+        assert r["new"] == sorted(_as_ids(fx, b["new"]))
+        assert r["del"] == sorted(_as_ids(fx, b["subsumed"]))
+
+
+@pytest.mark.parametrize("n", [3, 5, 12, 30])
+def test_imce_complete_minus_one_edge(n):
+    iu, ju = np.triu_indices(n, 1)
+    keep = ~((iu == 0) & (ju == n - 1))
+    g = gg.csr_from_edges(n, iu[keep], ju[keep])
+    st = O.Imce(g)
+    r = st.add([0], [n - 1], cliques=True, check_form=True)
+    assert r["new"] == [tuple(range(n))]
+    assert r["del"] == sorted([tuple(range(1, n)), tuple(range(n - 1))])
+    assert (r["n_new"], r["n_del"]) == (1, 2)
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 7])
+def test_imce_moon_moser_plus_one_edge(k):
+    g = gg.moon_moser(3 * k)
+    st = O.Imce(g)
+    r = st.add([0], [1], check_form=True)  # two vertices of the first part
+    assert (r["n_new"], r["n_del"]) == (3 ** (k - 1), 2 * 3 ** (k - 1))
+    assert r["count"] == 3 ** k - 3 ** (k - 1)
+
+
+def test_imce_batch_canonicalisation():
+    g = gg.from_edge_list(6, [(0, 1), (1, 2)])
+    st = O.Imce(g)
+    with pytest.raises(ValueError):
+        st.add([0], [0])
+    with pytest.raises(ValueError):
+        st.add([0], [9])
+    assert st.snapshot()[0] == 5  # state unchanged by rejected batches
+    r = st.add([1, 2, 0, 3], [0, 1, 2, 4])  # (1,0) (2,1) exist; (0,2) new; (3,4) new
+    assert (r["n_applied"], r["n_skipped"]) == (2, 2)
+    r = st.add([4, 3, 3], [3, 4, 5])  # (4,3) exists, (3,4) exists, (3,5) new
+    assert (r["n_applied"], r["n_skipped"]) == (1, 2)
+    r = st.add([], [])
+    assert (r["n_applied"], r["n_new"], r["n_del"]) == (0, 0, 0)
+
+
+def _recompute_diff(g_old, g_new):
+    old = set(O.mce_root(g_old, cliques=True)[3])
+    new = set(O.mce_root(g_new, cliques=True)[3])
+    return sorted(new - old), sorted(old - new)
+
+
+def test_imce_random_streams_equal_recompute_and_diff():
+    for seed in range(12):
+        n = 12 + seed * 2
+        g = gg.er(n, 0.15 + 0.02 * seed, seed=seed)
+        st = O.Imce(g)
+        stream = gg.edge_stream(g, 4, 1, 6, seed=50 + seed)
+        cur = g
+        for s, d in stream:
+            nxt = gg.add_edges(cur, s, d)
+            want_new, want_del = _recompute_diff(cur, nxt)
+            r = st.add(s, d, cliques=True, check_form=True)
+            assert r["new"] == want_new and r["del"] == want_del
+            c, h = st.snapshot()
+            c2, h2, _ = O.mce_root(nxt)
+            assert (c, h) == (c2, h2)
+            cur = nxt
