@@ -1,0 +1,179 @@
+/*
+ * mce.h - C ABI of the MI355X (gfx950) maximal clique enumeration library.
+ *
+ * The library implements the shared-memory method of Das, Sanei-Mehri and
+ * Tirthapura, "Shared-Memory Parallel Maximal Clique Enumeration from Static
+ * and Dynamic Graphs", as GPU kernels:
+ *   - mce_static: every maximal clique of a simple undirected graph.  The
+ *     problem is split into one subproblem per vertex v (Algorithm 4,
+ *     ParMCE): K = {v}, cand = neighbours of higher rank, fini = the rest;
+ *     each subproblem is searched by pivoted backtracking (Algorithm 1, TTT;
+ *     its unrolled form, Algorithm 3, gives independent children, which the
+ *     GPU work queue uses to split large subproblems).
+ *   - imce_*: incremental maintenance under batches of edge additions
+ *     (Section 5): the new maximal cliques of G+H (Algorithms 5, 6 and 8) and
+ *     the cliques of G they subsume (Algorithm 7).
+ *
+ * Conventions
+ *   - A graph is a CSR over vertex ids 0..n-1: row_ptr[n+1] (uint64),
+ *     col[row_ptr[n]] (uint32).  Rows are sorted ascending, the adjacency is
+ *     symmetric, and there are no self-loops or repeated entries (a simple
+ *     undirected graph, Section 3).  An isolated vertex v forms the maximal
+ *     clique {v}; n = 0 has no maximal cliques.
+ *   - `on_device` != 0 means the pointer is HIP device memory of the current
+ *     device; 0 means host memory.  Input arrays are borrowed for the call.
+ *   - Every call runs on `opts->hip_stream` (NULL = the default stream) and
+ *     returns after the results are complete.
+ *   - Return values: MCE_OK (0) or a negative MCE_E* code; mce_strerror()
+ *     names it and mce_last_error() gives the calling thread's last detailed
+ *     message.  On error the output structs are unspecified unless stated.
+ *   - The clique-set hash of a set S of cliques is
+ *         H(S) = sum over c in S of hc(c)            (mod 2^64)
+ *         hc(c) = mix(sum over v in c of mix(v) + |c| * 0x9E3779B97F4A7C15)
+ *     with mix the splitmix64 output function (add 0x9E3779B97F4A7C15, then
+ *     x ^= x>>30; x *= 0xBF58476D1CE4E5B9; x ^= x>>27; x *= 0x94D049BB133111EB;
+ *     x ^= x>>31).  It does not depend on the order of cliques or of vertices.
+ *   - The pivot of a search node is, among the vertices u of cand u fini that
+ *     maximise |cand n Gamma(u)|, the one with the smallest id; the children
+ *     are visited in ascending id.  With these two choices the recursion tree,
+ *     and so the node count, is fully determined.
+ */
+#ifndef MCE_MI355X_H
+#define MCE_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCE_OK 0
+#define MCE_EINVAL (-1)  /* bad argument: malformed CSR, id >= n, self-loop in a batch, NULL pointer */
+#define MCE_ENOMEM (-2)  /* device allocation failed */
+#define MCE_ENOSPC (-3)  /* a caller clique buffer is too small; required sizes written back */
+#define MCE_EDEVICE (-4) /* HIP runtime error */
+#define MCE_ENOTSUP (-5) /* input outside the supported envelope (see mce_static) */
+
+typedef struct {
+  uint64_t n;               /* number of vertices */
+  const uint64_t* row_ptr;  /* n+1 entries, row_ptr[0] = 0 */
+  const uint32_t* col;      /* row_ptr[n] entries */
+  int on_device;
+} mce_csr;
+
+/* Rank used to give each clique to exactly one subproblem (Section 4.2):
+ * rank(v) = (metric(v), id(v)) compared lexicographically, metric = degree,
+ * core number (degeneracy), or number of triangles through v.  Subproblem v
+ * reports exactly the cliques in which v has the lowest rank. */
+typedef enum { MCE_RANK_DEGREE = 0, MCE_RANK_DEGENERACY = 1, MCE_RANK_TRIANGLE = 2 } mce_rank;
+
+/* Order in which subproblems enter the work queue (largest key first).  It
+ * changes only the schedule, never the cliques, hashes or node counts. */
+typedef enum {
+  MCE_SCHED_DEGREE = 0,   /* vertex degree */
+  MCE_SCHED_TRIANGLE = 1, /* triangles through the vertex */
+  MCE_SCHED_COST = 2,     /* caller-supplied per-vertex cost (e.g. a learned cost model) */
+  MCE_SCHED_ID = 3        /* ascending vertex id */
+} mce_sched;
+
+typedef struct {
+  mce_sched sched;
+  int validate;             /* != 0: check the CSR on the device first (MCE_EINVAL if malformed) */
+  void* hip_stream;         /* hipStream_t; NULL = default stream */
+  const float* sched_cost;  /* MCE_SCHED_COST: device array of n costs, larger = scheduled earlier */
+  /* tuner overrides, 0 = library default */
+  uint32_t waves_per_cu;    /* persistent enumeration waves per compute unit */
+  uint32_t donate_interval; /* search nodes between checks for idle waves */
+  uint32_t frame_cap;       /* initial DFS frames per wave (grows on demand) */
+  uint32_t reserved[5];
+} mce_opts;
+
+typedef struct {
+  uint64_t count;       /* number of maximal cliques */
+  uint64_t set_hash;    /* H(all maximal cliques) */
+  uint64_t nodes_total; /* search nodes (TTT invocations, subproblem roots included) */
+  uint64_t donated;     /* subtrees handed to idle waves */
+  uint64_t subproblems; /* subproblems that needed a search (|cand| > 0) */
+  uint64_t max_cand;    /* largest |cand| of a subproblem */
+  double rank_ms, build_ms, enum_ms; /* device time of ranking, subproblem build + queue, enumeration */
+  uint32_t retries;     /* enumeration restarts after a DFS stack overflow */
+  uint32_t pad;
+} mce_result;
+
+/* Clique output in CSR form: clique i is vert[off[i] .. off[i+1]), vertices
+ * ascending; the order of cliques is unspecified.  The library writes
+ * n_cliques / n_verts (the required sizes) always, and the arrays only when
+ * both fit (off needs n_cliques+1 entries); otherwise the call returns
+ * MCE_ENOSPC after finishing all other outputs.  n_verts must stay below
+ * 2^32 per call. */
+typedef struct {
+  uint64_t cap_cliques, cap_verts;
+  uint64_t* off;
+  uint32_t* vert;
+  int on_device;
+  uint64_t n_cliques, n_verts;
+} mce_clique_buf;
+
+/* Optional per-subproblem outputs, device arrays of n entries each (any may be
+ * NULL): search nodes, cliques and H(cliques) of subproblem v.  Node counts
+ * are the labels of the learned cost model. */
+typedef struct {
+  uint64_t* nodes;
+  uint64_t* count;
+  uint64_t* hash;
+} mce_per_vertex;
+
+/* All maximal cliques of `g` (Algorithm 4 over Algorithm 1).
+ * opts may be NULL (defaults), cliques and per_vertex may be NULL.
+ * Supported envelope: n < 2^32, |cand| of every subproblem <= 4096 (else
+ * MCE_ENOTSUP), and for materialised output n_verts < 2^32. */
+int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
+               mce_clique_buf* cliques, const mce_per_vertex* per_vertex);
+
+/* Per-vertex rank metric (Section 4.2) into the device array metric[n]. */
+int mce_rank_metric(const mce_csr* g, mce_rank rank, uint64_t* metric, void* hip_stream);
+
+/* Cost-model features of every vertex into the device array feat[n*4]
+ * (row-major, float): log1p of degree, core number, triangles through v, and
+ * the number of length-2 walks from v (sum over neighbours u of d(u)-1). */
+int mce_features(const mce_csr* g, float* feat, void* hip_stream);
+
+/* --- incremental maintenance (Section 5) -------------------------------- */
+
+typedef struct imce_state imce_state; /* opaque: device graph, clique count and set hash */
+
+typedef struct {
+  uint64_t n_applied;  /* batch edges added (after canonicalisation) */
+  uint64_t n_skipped;  /* batch edges already in G or repeated in the batch */
+  uint64_t n_new;      /* |Lambda_new| = |C(G+H) \ C(G)| */
+  uint64_t n_del;      /* |Lambda_del| = |C(G) \ C(G+H)| */
+  uint64_t hash_new, hash_del; /* H(Lambda_new), H(Lambda_del) */
+  uint64_t count, set_hash;    /* |C(G+H)| and H(C(G+H)) after the batch */
+  double new_ms, sub_ms, ms;   /* device time: new cliques, subsumed cliques, whole batch */
+} imce_result;
+
+/* Copies `g` to state-owned device memory and enumerates C(g) once (degree
+ * ranking) to initialise the count and set hash.  `initial` may be NULL. */
+int imce_create(const mce_csr* g, const mce_opts* opts, imce_state** out, mce_result* initial);
+
+/* Adds the batch H = {(src[i], dst[i])}.  Every pair must have two distinct
+ * ids < n, else MCE_EINVAL and the state is unchanged.  Pairs already in G or
+ * repeated in the batch are skipped (n_skipped); the survivors, in input
+ * order, are e_1..e_rho of Algorithm 5.  new_cl / del_cl (nullable) receive
+ * Lambda_new / Lambda_del.  On any error the state is unchanged (the batch is
+ * applied atomically). */
+int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                   imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
+
+/* Current graph: n and the number of stored adjacency entries (2m). */
+int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash);
+
+void imce_destroy(imce_state* st);
+
+const char* mce_strerror(int code);
+const char* mce_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCE_MI355X_H */

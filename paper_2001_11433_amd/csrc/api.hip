@@ -1,0 +1,537 @@
+// Host side of the C ABI: argument checks, device workspace, the static MCE
+// pipeline (rank -> subproblem build -> queue -> persistent enumeration) and
+// error reporting.  No computation of the method happens on the host; it
+// only sizes buffers and launches kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace mce {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t b) {
+    if (b <= bytes && p) return MCE_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t want = std::max<size_t>(b, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? MCE_ENOMEM : MCE_EDEVICE;
+    }
+    bytes = want;
+    return MCE_OK;
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+// Device workspace of the static pipeline; grown on demand, reused across
+// calls on the same device, guarded by one mutex per device.
+struct Workspace {
+  DevBuf rp, col, metric, tri, core, coredeg, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
+      gids, keys, vals, keys2, vals2, queue, ctl, pool, stacks, iota, clq_off, clq_vert, bad;
+  void* scan_tmp = nullptr;
+  size_t scan_bytes = 0;
+  void* sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+};
+
+std::mutex g_mu[64];
+Workspace g_ws[64];
+
+int current_device(int* dev) {
+  MCE_TRY_HIP(hipGetDevice(dev));
+  if (*dev < 0 || *dev >= 64) {
+    set_error("device index %d out of range", *dev);
+    return MCE_ENOTSUP;
+  }
+  return MCE_OK;
+}
+
+int cu_count() {
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+  return cu;
+}
+
+__global__ void k_iota(uint64_t n, uint32_t* a) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (uint32_t)i;
+}
+
+// Singletons {v} of isolated vertices, for materialised output.
+__global__ void k_emit_isolated(uint64_t n, const uint64_t* __restrict__ rp, uint64_t* ctl, uint64_t* off,
+                                uint32_t* vert, uint64_t cap_c, uint64_t cap_v) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n || rp[v + 1] != rp[v]) return;
+  uint64_t old = atomicAdd((unsigned long long*)&ctl[CTL_CLQ], (unsigned long long)((1ULL << 32) | 1ULL));
+  uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+  if (id < cap_c && pos + 1 <= cap_v) {
+    off[id] = pos;
+    vert[pos] = (uint32_t)v;
+  }
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
+
+struct Timer {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Timer() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  int init() {
+    for (auto& x : e) MCE_TRY_HIP(hipEventCreate(&x));
+    return MCE_OK;
+  }
+  double ms(int a, int b) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0;
+    return t;
+  }
+};
+
+mce_opts default_opts() {
+  mce_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.sched = MCE_SCHED_DEGREE;
+  return o;
+}
+
+// Host view of the input: either borrowed device pointers or an upload.
+int stage_csr(const mce_csr* g, Workspace& ws, hipStream_t s, const uint64_t** rp, const uint32_t** col,
+              uint64_t* nnz) {
+  const uint64_t n = g->n;
+  if (n > 0 && !g->row_ptr) {
+    set_error("row_ptr is NULL");
+    return MCE_EINVAL;
+  }
+  if (g->on_device) {
+    uint64_t last = 0;
+    if (n > 0) {
+      MCE_TRY_HIP(hipMemcpyAsync(&last, g->row_ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      MCE_TRY_HIP(hipStreamSynchronize(s));
+    }
+    *nnz = last;
+    *rp = g->row_ptr;
+    *col = g->col;
+  } else {
+    *nnz = n ? g->row_ptr[n] : 0;
+    MCE_TRY(ws.rp.ensure((n + 1) * sizeof(uint64_t)));
+    MCE_TRY(ws.col.ensure(std::max<uint64_t>(*nnz, 1) * sizeof(uint32_t)));
+    if (n > 0) MCE_TRY_HIP(hipMemcpyAsync(ws.rp.p, g->row_ptr, (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if (*nnz) MCE_TRY_HIP(hipMemcpyAsync(ws.col.p, g->col, *nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    *rp = ws.rp.as<uint64_t>();
+    *col = ws.col.as<uint32_t>();
+  }
+  if (*nnz > 0 && !g->col) {
+    set_error("col is NULL");
+    return MCE_EINVAL;
+  }
+  if (*nnz >= (1ULL << 40)) {
+    set_error("graph too large");
+    return MCE_ENOTSUP;
+  }
+  return MCE_OK;
+}
+
+int validate_csr(uint64_t n, const uint64_t* rp, const uint32_t* col, Workspace& ws, hipStream_t s) {
+  MCE_TRY(ws.bad.ensure(sizeof(uint32_t)));
+  MCE_TRY_HIP(hipMemsetAsync(ws.bad.p, 0, sizeof(uint32_t), s));
+  uint64_t first = 1;
+  if (n) {
+    MCE_TRY_HIP(hipMemcpyAsync(&first, rp, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  }
+  MCE_TRY_HIP(launch_validate(n, rp, col, ws.bad.as<uint32_t>(), s));
+  uint32_t bad = 0;
+  MCE_TRY_HIP(hipMemcpyAsync(&bad, ws.bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  if (n && first != 0) {
+    set_error("row_ptr[0] != 0");
+    return MCE_EINVAL;
+  }
+  if (bad) {
+    set_error("malformed CSR (code %u: 1 row_ptr decreasing, 2 bad/unsorted/self-loop column, 4 asymmetric)", bad);
+    return MCE_EINVAL;
+  }
+  return MCE_OK;
+}
+
+int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* metric,
+                   Workspace& ws, hipStream_t s) {
+  switch (rank) {
+    case MCE_RANK_DEGREE:
+      MCE_TRY_HIP(launch_degree(n, rp, metric, s));
+      return MCE_OK;
+    case MCE_RANK_DEGENERACY:
+      MCE_TRY(ws.coredeg.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
+      MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
+      return run_core_numbers(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corectl.as<uint64_t>(), s);
+    case MCE_RANK_TRIANGLE:
+      MCE_TRY_HIP(launch_triangles(n, rp, col, metric, s));
+      return MCE_OK;
+  }
+  set_error("unknown rank %d", (int)rank);
+  return MCE_EINVAL;
+}
+
+int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_result* out, mce_clique_buf* cl,
+                const mce_per_vertex* pv, Workspace& ws) {
+  hipStream_t s = (hipStream_t)opts.hip_stream;
+  const uint64_t n = g->n;
+  if (n >= 0xFFFFFFFFULL) {
+    set_error("n must be below 2^32 - 1");
+    return MCE_ENOTSUP;
+  }
+  if (rank != MCE_RANK_DEGREE && rank != MCE_RANK_DEGENERACY && rank != MCE_RANK_TRIANGLE) {
+    set_error("unknown rank %d", (int)rank);
+    return MCE_EINVAL;
+  }
+  if (opts.sched == MCE_SCHED_COST && !opts.sched_cost) {
+    set_error("MCE_SCHED_COST needs sched_cost");
+    return MCE_EINVAL;
+  }
+  if ((unsigned)opts.sched > MCE_SCHED_ID) {
+    set_error("unknown schedule %d", (int)opts.sched);
+    return MCE_EINVAL;
+  }
+  if (cl && ((cl->cap_cliques && !cl->off) || (cl->cap_verts && !cl->vert))) {
+    set_error("clique buffer has capacity but no array");
+    return MCE_EINVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  const uint64_t* rp;
+  const uint32_t* col;
+  uint64_t nnz;
+  MCE_TRY(stage_csr(g, ws, s, &rp, &col, &nnz));
+  if (n == 0) {
+    if (cl) {
+      cl->n_cliques = 0;
+      cl->n_verts = 0;
+      if (cl->cap_cliques >= 0 && cl->off) {
+        uint64_t z = 0;
+        if (cl->on_device) MCE_TRY_HIP(hipMemcpyAsync(cl->off, &z, sizeof(z), hipMemcpyHostToDevice, s));
+        else cl->off[0] = 0;
+      }
+      MCE_TRY_HIP(hipStreamSynchronize(s));
+    }
+    return MCE_OK;
+  }
+  if (opts.validate) MCE_TRY(validate_csr(n, rp, col, ws, s));
+
+  Timer tm;
+  MCE_TRY(tm.init());
+  MCE_TRY_HIP(hipEventRecord(tm.e[0], s));
+
+  // --- rank (Section 4.2)
+  MCE_TRY(ws.metric.ensure(n * sizeof(uint64_t)));
+  uint64_t* metric = ws.metric.as<uint64_t>();
+  MCE_TRY(compute_metric(rank, n, rp, col, metric, ws, s));
+  const uint64_t* tri = nullptr;
+  if (opts.sched == MCE_SCHED_TRIANGLE) {
+    if (rank == MCE_RANK_TRIANGLE) {
+      tri = metric;
+    } else {
+      MCE_TRY(ws.tri.ensure(n * sizeof(uint64_t)));
+      MCE_TRY_HIP(launch_triangles(n, rp, col, ws.tri.as<uint64_t>(), s));
+      tri = ws.tri.as<uint64_t>();
+    }
+  }
+  MCE_TRY_HIP(hipEventRecord(tm.e[1], s));
+
+  // --- subproblem sizes and build (Algorithm 4, body)
+  MCE_TRY(ws.P.ensure(n * sizeof(uint32_t)));
+  MCE_TRY(ws.X.ensure(n * sizeof(uint32_t)));
+  MCE_TRY(ws.words.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.gwords.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.off.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.goff.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.stats.ensure(8 * sizeof(uint64_t)));
+  const uint64_t xwords = std::max<uint64_t>((nnz + 31) / 32, 1);
+  MCE_TRY(ws.xmark.ensure(xwords * sizeof(uint32_t)));
+  MCE_TRY(ws.lidx.ensure(std::max<uint64_t>(nnz, 1) * sizeof(uint32_t)));
+  BuildBufs b;
+  b.p = ws.P.as<uint32_t>();
+  b.x = ws.X.as<uint32_t>();
+  b.xmark = ws.xmark.as<uint32_t>();
+  b.lidx = ws.lidx.as<uint32_t>();
+  b.words = ws.words.as<uint64_t>();
+  b.gwords = ws.gwords.as<uint64_t>();
+  b.stats = ws.stats.as<uint64_t>();
+  uint64_t* nodes_v = pv ? pv->nodes : nullptr;
+  uint64_t* count_v = pv ? pv->count : nullptr;
+  uint64_t* hash_v = pv ? pv->hash : nullptr;
+
+  MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
+  MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
+  MCE_TRY_HIP(hipMemsetAsync(b.xmark, 0, xwords * sizeof(uint32_t), s));
+  MCE_TRY_HIP(launch_mark(n, rp, col, metric, b, s));
+  MCE_TRY_HIP(launch_words(n, rp, b, s));
+  MCE_TRY(device_exclusive_scan(b.words, ws.off.as<uint64_t>(), n, ws.scan_tmp, ws.scan_bytes, s));
+  MCE_TRY(device_exclusive_scan(b.gwords, ws.goff.as<uint64_t>(), n, ws.scan_tmp, ws.scan_bytes, s));
+  uint64_t stats[8], tail[4];
+  MCE_TRY_HIP(hipMemcpyAsync(stats, b.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tail[0], ws.off.as<uint64_t>() + n - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tail[1], b.words + n - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tail[2], ws.goff.as<uint64_t>() + n - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tail[3], b.gwords + n - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  const uint64_t max_p = stats[0], max_frame = stats[1], nq = stats[2];
+  out->subproblems = nq;
+  out->max_cand = max_p;
+  if (max_p > kMaxCand) {
+    set_error("a subproblem has %llu candidates; at most %u are supported", (unsigned long long)max_p, kMaxCand);
+    return MCE_ENOTSUP;
+  }
+  const uint64_t arena_words = tail[0] + tail[1], gid_words = tail[2] + tail[3];
+  MCE_TRY(ws.arena.ensure(std::max<uint64_t>(arena_words, 1) * sizeof(uint64_t)));
+  MCE_TRY(ws.gids.ensure(std::max<uint64_t>(gid_words, 1) * sizeof(uint32_t)));
+  MCE_TRY_HIP(hipMemsetAsync(ws.arena.p, 0, std::max<uint64_t>(arena_words, 1) * sizeof(uint64_t), s));
+  MCE_TRY_HIP(launch_build(n, rp, col, metric, b, ws.off.as<uint64_t>(), ws.goff.as<uint64_t>(),
+                           ws.arena.as<uint64_t>(), ws.gids.as<uint32_t>(), s));
+
+  // --- queue order (never changes results)
+  MCE_TRY(ws.keys.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.keys2.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.vals.ensure(n * sizeof(uint32_t)));
+  MCE_TRY(ws.vals2.ensure(n * sizeof(uint32_t)));
+  MCE_TRY_HIP(launch_queue_keys(n, rp, b.p, opts.sched, tri, opts.sched_cost, ws.keys.as<uint64_t>(),
+                                ws.vals.as<uint32_t>(), nullptr, s));
+  uint64_t* skeys;
+  uint32_t* svals;
+  MCE_TRY(device_sort_desc(ws.keys.as<uint64_t>(), ws.vals.as<uint32_t>(), ws.keys2.as<uint64_t>(),
+                           ws.vals2.as<uint32_t>(), n, ws.sort_tmp, ws.sort_bytes, s, &skeys, &svals));
+  const uint64_t max_tickets = std::max<uint64_t>(1u << 20, 4 * nq);
+  const uint64_t qcap = nq + max_tickets;
+  MCE_TRY(ws.queue.ensure(qcap * sizeof(uint64_t)));
+  MCE_TRY(ws.iota.ensure(n * sizeof(uint32_t)));
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ws.iota.as<uint32_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  MCE_TRY_HIP(hipEventRecord(tm.e[2], s));
+
+  // --- clique output buffers
+  uint64_t* cl_off = nullptr;
+  uint32_t* cl_vert = nullptr;
+  if (cl) {
+    if (cl->on_device) {
+      cl_off = cl->off;
+      cl_vert = cl->vert;
+    } else {
+      MCE_TRY(ws.clq_off.ensure((cl->cap_cliques + 1) * sizeof(uint64_t)));
+      MCE_TRY(ws.clq_vert.ensure(std::max<uint64_t>(cl->cap_verts, 1) * sizeof(uint32_t)));
+      cl_off = ws.clq_off.as<uint64_t>();
+      cl_vert = ws.clq_vert.as<uint32_t>();
+    }
+  }
+
+  // --- persistent enumeration, restarted with deeper stacks on overflow
+  const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
+  const uint32_t grid = (uint32_t)cu_count() * wpc;
+  uint32_t frame_cap = opts.frame_cap ? opts.frame_cap : 128;
+  frame_cap = std::min<uint32_t>(frame_cap, (uint32_t)max_p + 2);
+  const uint64_t pool_cap = 1ULL << 26;  // 512 MiB of task records
+  MCE_TRY(ws.pool.ensure(pool_cap * sizeof(uint64_t)));
+  MCE_TRY(ws.ctl.ensure(CTL_WORDS * sizeof(uint64_t)));
+  uint64_t ctl[CTL_WORDS];
+  for (uint32_t attempt = 0;; ++attempt) {
+    if (attempt > 0) {
+      // results of the aborted run are discarded: reset per-vertex outputs
+      MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
+      MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
+    }
+    const uint64_t stack_words = (uint64_t)frame_cap * std::max<uint64_t>(max_frame + 1, 8);
+    MCE_TRY(ws.stacks.ensure((uint64_t)grid * stack_words * sizeof(uint64_t)));
+    MCE_TRY_HIP(hipMemsetAsync(ws.queue.p, 0, qcap * sizeof(uint64_t), s));
+    MCE_TRY_HIP(launch_queue_fill(nq, svals, ws.queue.as<uint64_t>(), s));
+    std::memset(ctl, 0, sizeof(ctl));
+    ctl[CTL_TAIL] = nq;
+    ctl[CTL_PENDING] = nq;
+    MCE_TRY_HIP(hipMemcpyAsync(ws.ctl.p, ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
+    if (cl) {
+      hipLaunchKernelGGL(k_emit_isolated, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, ws.ctl.as<uint64_t>(),
+                         cl_off, cl_vert, cl->cap_cliques, cl->cap_verts);
+      MCE_TRY_HIP(hipGetLastError());
+    }
+    EnumArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sub.off = ws.off.as<uint64_t>();
+    a.sub.goff = ws.goff.as<uint64_t>();
+    a.sub.p = b.p;
+    a.sub.x = b.x;
+    a.sub.r0 = ws.iota.as<uint32_t>();
+    a.sub.r1 = ws.iota.as<uint32_t>();
+    a.arena = ws.arena.as<uint64_t>();
+    a.gids = ws.gids.as<uint32_t>();
+    a.queue = ws.queue.as<uint64_t>();
+    a.qcap = qcap;
+    a.ctl = ws.ctl.as<uint64_t>();
+    a.pool = ws.pool.as<uint64_t>();
+    a.pool_cap = pool_cap;
+    a.max_tickets = max_tickets;
+    a.stacks = ws.stacks.as<uint64_t>();
+    a.stack_words = stack_words;
+    a.frame_cap = frame_cap;
+    a.frame_words = (uint32_t)max_frame + 1;
+    a.donate_interval = opts.donate_interval ? opts.donate_interval : 32;
+    a.nodes_v = nodes_v;
+    a.count_v = count_v;
+    a.hash_v = hash_v;
+    a.cl_off = cl_off;
+    a.cl_vert = cl_vert;
+    a.cap_cliques = cl ? cl->cap_cliques : 0;
+    a.cap_verts = cl ? cl->cap_verts : 0;
+    if (nq > 0) MCE_TRY_HIP(launch_enum(a, grid, false, s));
+    MCE_TRY_HIP(hipEventRecord(tm.e[3], s));
+    MCE_TRY_HIP(hipMemcpyAsync(ctl, ws.ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipMemcpyAsync(stats, b.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    if (!(ctl[CTL_FLAGS] & 1ULL)) break;
+    if (frame_cap >= max_p + 2 || attempt >= 12) {
+      set_error("DFS stack overflow at %u frames", frame_cap);
+      return MCE_ENOMEM;
+    }
+    frame_cap = std::min<uint32_t>(frame_cap * 2, (uint32_t)max_p + 2);
+    out->retries = attempt + 1;
+  }
+  out->count = stats[3] + ctl[CTL_COUNT];
+  out->set_hash = stats[4] + ctl[CTL_HASH];
+  out->nodes_total = stats[5] + ctl[CTL_NODES];
+  out->donated = ctl[CTL_DONATED];
+  out->rank_ms = tm.ms(0, 1);
+  out->build_ms = tm.ms(1, 2);
+  out->enum_ms = tm.ms(2, 3);
+  int rc = MCE_OK;
+  if (cl) {
+    const uint64_t nc = ctl[CTL_CLQ] >> 32, nv = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
+    cl->n_cliques = nc;
+    cl->n_verts = nv;
+    if (ctl[CTL_FLAGS] & 2ULL) {
+      set_error("materialised output exceeds 2^32 vertices or a clique exceeds 1024 vertices");
+      return MCE_ENOTSUP;
+    }
+    if (nc > cl->cap_cliques || nv > cl->cap_verts || !cl_off) {
+      set_error("clique buffer too small: need %llu cliques, %llu vertices", (unsigned long long)nc,
+                (unsigned long long)nv);
+      rc = MCE_ENOSPC;
+    } else {
+      MCE_TRY_HIP(launch_finish_offsets(cl_off, nc, nv, s));
+      if (!cl->on_device) {
+        MCE_TRY_HIP(hipMemcpyAsync(cl->off, cl_off, (nc + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        if (nv) MCE_TRY_HIP(hipMemcpyAsync(cl->vert, cl_vert, nv * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      }
+      MCE_TRY_HIP(hipStreamSynchronize(s));
+    }
+  }
+  return rc;
+}
+
+}  // namespace
+}  // namespace mce
+
+using namespace mce;
+
+extern "C" {
+
+const char* mce_strerror(int code) {
+  switch (code) {
+    case MCE_OK: return "ok";
+    case MCE_EINVAL: return "invalid argument";
+    case MCE_ENOMEM: return "out of device memory";
+    case MCE_ENOSPC: return "output buffer too small";
+    case MCE_EDEVICE: return "HIP runtime error";
+    case MCE_ENOTSUP: return "input outside the supported envelope";
+  }
+  return "unknown error";
+}
+
+const char* mce_last_error(void) { return g_err; }
+
+int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out, mce_clique_buf* cliques,
+               const mce_per_vertex* per_vertex) {
+  if (!g || !out) {
+    set_error("NULL graph or result");
+    return MCE_EINVAL;
+  }
+  mce_opts o = opts ? *opts : default_opts();
+  int dev;
+  MCE_TRY(current_device(&dev));
+  std::lock_guard<std::mutex> lk(g_mu[dev]);
+  return static_impl(g, rank, o, out, cliques, per_vertex, g_ws[dev]);
+}
+
+int mce_rank_metric(const mce_csr* g, mce_rank rank, uint64_t* metric, void* hip_stream) {
+  if (!g || !metric) {
+    set_error("NULL graph or output");
+    return MCE_EINVAL;
+  }
+  int dev;
+  MCE_TRY(current_device(&dev));
+  std::lock_guard<std::mutex> lk(g_mu[dev]);
+  Workspace& ws = g_ws[dev];
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint64_t* rp;
+  const uint32_t* col;
+  uint64_t nnz;
+  MCE_TRY(stage_csr(g, ws, s, &rp, &col, &nnz));
+  if (g->n == 0) return MCE_OK;
+  MCE_TRY(compute_metric(rank, g->n, rp, col, metric, ws, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  return MCE_OK;
+}
+
+int mce_features(const mce_csr* g, float* feat, void* hip_stream) {
+  if (!g || !feat) {
+    set_error("NULL graph or output");
+    return MCE_EINVAL;
+  }
+  int dev;
+  MCE_TRY(current_device(&dev));
+  std::lock_guard<std::mutex> lk(g_mu[dev]);
+  Workspace& ws = g_ws[dev];
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint64_t* rp;
+  const uint32_t* col;
+  uint64_t nnz;
+  MCE_TRY(stage_csr(g, ws, s, &rp, &col, &nnz));
+  const uint64_t n = g->n;
+  if (n == 0) return MCE_OK;
+  MCE_TRY(ws.core.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(ws.tri.ensure(n * sizeof(uint64_t)));
+  MCE_TRY(compute_metric(MCE_RANK_DEGENERACY, n, rp, col, ws.core.as<uint64_t>(), ws, s));
+  MCE_TRY_HIP(launch_triangles(n, rp, col, ws.tri.as<uint64_t>(), s));
+  MCE_TRY_HIP(launch_features(n, rp, col, ws.core.as<uint64_t>(), ws.tri.as<uint64_t>(), feat, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  return MCE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mce.h"
+
+namespace mce {
+
+void set_error(const char* fmt, ...);
+
+#define MCE_TRY_HIP(expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::mce::set_error("%s:%d: %s: %s", __FILE__, __LINE__, #expr, hipGetErrorString(e_)); \
+      return (e_ == hipErrorOutOfMemory) ? MCE_ENOMEM : MCE_EDEVICE;                   \
+    }                                                                                  \
+  } while (0)
+
+#define MCE_TRY(expr)        \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != MCE_OK) return rc_; \
+  } while (0)
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kMaxCand = 4096;  // |cand| per subproblem: 64 words of 64 bits
+
+// Control block of one enumeration launch (uint64 words).
+enum {
+  CTL_HEAD = 0,      // next queue slot to claim
+  CTL_TAIL = 1,      // next queue slot to fill
+  CTL_PENDING = 2,   // tasks queued or running
+  CTL_POOL = 3,      // task-record pool bump pointer (words)
+  CTL_TICKETS = 4,   // donation tickets handed out
+  CTL_FLAGS = 5,     // bit 0: DFS stack overflow; bit 1: clique counter overflow
+  CTL_DONATED = 6,   // donations that reached the queue
+  CTL_CLQ = 7,       // packed clique-output counter: (cliques << 32) | verts
+  CTL_COUNT = 8,     // maximal cliques
+  CTL_HASH = 9,      // sum of clique hashes
+  CTL_NODES = 10,    // search nodes
+  CTL_WORDS = 16
+};
+
+// Per-subproblem tables, indexed by subproblem id.
+struct SubTab {
+  const uint64_t* off;   // word offset of the subproblem's bit rows in the arena
+  const uint64_t* goff;  // offset of its vertex-id table
+  const uint32_t* p;     // |cand| at the root
+  const uint32_t* x;     // number of fini vertices that have a cand neighbour
+  const uint32_t* r0;    // root clique vertex
+  const uint32_t* r1;    // second root clique vertex (edge subproblems) or kNone
+};
+
+struct EnumArgs {
+  SubTab sub;
+  const uint64_t* arena;
+  const uint32_t* gids;
+  uint64_t* queue;
+  uint64_t qcap;
+  uint64_t* ctl;
+  uint64_t* pool;
+  uint64_t pool_cap;
+  uint64_t max_tickets;
+  uint64_t* stacks;
+  uint64_t stack_words;  // per wave
+  uint32_t frame_cap;
+  uint32_t frame_words;  // max frame size over all subproblems
+  uint32_t donate_interval;
+  uint32_t pad;
+  uint64_t* nodes_v;     // per-subproblem outputs (nullable)
+  uint64_t* count_v;
+  uint64_t* hash_v;
+  uint64_t* cl_off;      // clique output (nullable)
+  uint32_t* cl_vert;
+  uint64_t cap_cliques, cap_verts;
+};
+
+// rank.hip
+hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s);
+hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipStream_t s);
+int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg_scratch,
+                     uint64_t* ctl_scratch, hipStream_t s);
+hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s);
+hipError_t launch_features(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* core,
+                           const uint64_t* tri, float* feat, hipStream_t s);
+
+// build.hip
+struct BuildBufs {
+  uint32_t* p;       // [n]
+  uint32_t* x;       // [n]
+  uint32_t* xmark;   // [ceil(2m/32)] fini vertices with a cand neighbour, by CSR position
+  uint32_t* lidx;    // [2m] local index of each CSR position in its row's subproblem
+  uint64_t* words;   // [n] arena words per subproblem (scan input/output)
+  uint64_t* gwords;  // [n]
+  uint64_t* stats;   // [8]: 0 max p, 1 max frame words, 2 nontrivial count, 3 count, 4 hash, 5 nodes
+};
+hipError_t launch_sizes(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* metric,
+                        BuildBufs b, uint64_t* nodes_v, uint64_t* count_v, uint64_t* hash_v, hipStream_t s);
+hipError_t launch_mark(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* metric, BuildBufs b,
+                       hipStream_t s);
+hipError_t launch_words(uint64_t n, const uint64_t* rp, BuildBufs b, hipStream_t s);
+hipError_t launch_build(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* metric, BuildBufs b,
+                        const uint64_t* off, const uint64_t* goff, uint64_t* arena, uint32_t* gids, hipStream_t s);
+hipError_t launch_queue_keys(uint64_t n, const uint64_t* rp, const uint32_t* p, mce_sched sched,
+                             const uint64_t* tri, const float* cost, uint64_t* keys, uint32_t* vals,
+                             uint64_t* count, hipStream_t s);
+hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, uint64_t* queue, hipStream_t s);
+int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& tmp, size_t& tmp_bytes,
+                          hipStream_t s);
+int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint64_t n,
+                     void*& tmp, size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out);
+
+// enum.hip
+hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
+hipError_t launch_finish_offsets(uint64_t* off, uint64_t n_cliques, uint64_t n_verts, hipStream_t s);
+
+}  // namespace mce

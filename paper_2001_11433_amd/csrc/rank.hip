@@ -1,0 +1,194 @@
+// Vertex metrics behind the rank functions of Section 4.2 (degree, core
+// number, triangle count), the cost-model features, and CSR validation.
+// All integer work; bound by HBM/L2 gathers over the adjacency.
+
+#include <math.h>
+
+#include "dev.h"
+#include "internal.h"
+
+namespace mce {
+
+namespace {
+
+__global__ void k_validate(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                           uint32_t* bad) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  uint64_t b = rp[v], e = rp[v + 1];
+  if (e < b) { atomicOr(bad, 1u); return; }
+  for (uint64_t i = b; i < e; ++i) {
+    uint32_t w = col[i];
+    if (w >= n || w == v || (i > b && w <= col[i - 1])) { atomicOr(bad, 2u); return; }
+    uint64_t wb = rp[w], we = rp[w + 1];
+    if (we < wb || bsearch_u32(col + wb, we - wb, (uint32_t)v) < 0) { atomicOr(bad, 4u); return; }
+  }
+}
+
+__global__ void k_degree(uint64_t n, const uint64_t* __restrict__ rp, uint64_t* __restrict__ metric) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v < n) metric[v] = rp[v + 1] - rp[v];
+}
+
+// --- core numbers: level-synchronous peeling --------------------------------
+// ctl: [0] level k, [1] removed in this round, [2] min remaining degree seen,
+//      [3] vertices remaining.
+constexpr uint64_t kAlive = ~0ULL;
+
+__global__ void k_core_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_t* deg, uint64_t* core,
+                            uint64_t* ctl) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v < n) {
+    deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
+    core[v] = kAlive;
+  }
+  if (v == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = ~0ULL;
+    ctl[3] = n;
+  }
+}
+
+// One round at level k: every alive vertex of remaining degree <= k leaves
+// with core number k and decrements its alive neighbours.  A vertex whose
+// degree drops to <= k during the round leaves in the next round.
+__global__ void k_core_round(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                             uint32_t* deg, uint64_t* core, uint64_t* ctl) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t k = ctl[0];
+  bool removed = false;
+  if (v < n && core[v] == kAlive) {
+    uint32_t d = __hip_atomic_load(&deg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d <= k) {
+      core[v] = k;
+      removed = true;
+      for (uint64_t i = rp[v]; i < rp[v + 1]; ++i) {
+        uint32_t w = col[i];
+        if (core[w] == kAlive) atomicSub(&deg[w], 1u);
+      }
+    } else {
+      atomicMin((unsigned long long*)&ctl[2], (unsigned long long)d);
+    }
+  }
+  uint64_t cnt = __popcll(ballot(removed));
+  if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)cnt);
+}
+
+// After a round: if nobody left, every alive degree is exact and > k, so the
+// next level is the smallest of them.
+__global__ void k_core_advance(uint64_t* ctl) {
+  uint64_t removed = ctl[1];
+  ctl[3] -= removed;
+  if (removed == 0 && ctl[3] > 0) ctl[0] = ctl[2];
+  ctl[1] = 0;
+  ctl[2] = ~0ULL;
+}
+
+// --- triangles -------------------------------------------------------------
+// One wave per vertex v.  Each triangle is found once, from its lowest vertex
+// in the order (degree, id): v < u < w; all three endpoints are credited.
+__device__ __forceinline__ bool deg_less(const uint64_t* rp, uint32_t a, uint32_t b) {
+  uint64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+  return da < db || (da == db && a < b);
+}
+
+__global__ void __launch_bounds__(256) k_triangles(uint64_t n, const uint64_t* __restrict__ rp,
+                                                   const uint32_t* __restrict__ col, uint64_t* tri) {
+  const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (v >= n) return;
+  const uint64_t vb = rp[v], ve = rp[v + 1];
+  uint64_t tv = 0;
+  for (uint64_t i = vb; i < ve; ++i) {
+    uint32_t u = col[i];
+    if (!deg_less(rp, (uint32_t)v, u)) continue;
+    const uint64_t ub = rp[u], ue = rp[u + 1];
+    uint64_t tu = 0;
+    for (uint64_t j = ub + lane; j < ue; j += kWave) {
+      uint32_t w = col[j];
+      if (deg_less(rp, u, w) && bsearch_u32(col + vb, ve - vb, w) >= 0) {
+        ++tu;
+        atomicAdd((unsigned long long*)&tri[w], 1ULL);
+      }
+    }
+    tu = wave_sum_u64(tu);
+    if (lane == 0 && tu) atomicAdd((unsigned long long*)&tri[u], (unsigned long long)tu);
+    tv += tu;
+  }
+  if (lane == 0 && tv) atomicAdd((unsigned long long*)&tri[v], (unsigned long long)tv);
+}
+
+__global__ void k_features(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                           const uint64_t* __restrict__ core, const uint64_t* __restrict__ tri,
+                           float* __restrict__ feat) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  uint64_t d = rp[v + 1] - rp[v];
+  uint64_t walks = 0;
+  for (uint64_t i = rp[v]; i < rp[v + 1]; ++i) {
+    uint32_t u = col[i];
+    walks += rp[u + 1] - rp[u] - 1;
+  }
+  feat[4 * v + 0] = log1pf((float)d);
+  feat[4 * v + 1] = log1pf((float)core[v]);
+  feat[4 * v + 2] = log1pf((float)tri[v]);
+  feat[4 * v + 3] = log1pf((float)walks);
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_degree, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, metric);
+  return hipGetLastError();
+}
+
+int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg,
+                     uint64_t* ctl, hipStream_t s) {
+  if (n == 0) return MCE_OK;
+  const uint32_t g = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_core_init, dim3(g), dim3(256), 0, s, n, rp, deg, core, ctl);
+  MCE_TRY_HIP(hipGetLastError());
+  // Rounds are enqueued in groups; the host only reads the remaining count
+  // between groups.  Extra rounds after the last vertex left are no-ops.
+  uint32_t group = 16;
+  for (;;) {
+    for (uint32_t r = 0; r < group; ++r) {
+      hipLaunchKernelGGL(k_core_round, dim3(g), dim3(256), 0, s, n, rp, col, deg, core, ctl);
+      hipLaunchKernelGGL(k_core_advance, dim3(1), dim3(1), 0, s, ctl);
+    }
+    MCE_TRY_HIP(hipGetLastError());
+    uint64_t remaining = 0;
+    MCE_TRY_HIP(hipMemcpyAsync(&remaining, ctl + 3, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    if (remaining == 0) break;
+    if (group < 256) group *= 2;
+  }
+  return MCE_OK;
+}
+
+hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(tri, 0, n * sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_triangles, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, tri);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* core,
+                           const uint64_t* tri, float* feat, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, core, tri, feat);
+  return hipGetLastError();
+}
+
+}  // namespace mce

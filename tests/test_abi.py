@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI: the library loads and exports every
+function declared in include/*.h.  No compute calls (no GPU here)."""
+
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M):
+            name = m.group(1)
+            if name not in ("if", "while", "for", "return", "sizeof"):
+                names.add(name)
+    return names
+
+
+def test_header_declares_the_entry_points():
+    d = _declared()
+    for name in ("mce_static", "imce_create", "imce_add_edges", "imce_destroy", "mce_strerror"):
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2001_11433_amd as m
+    L = m.lib()
+    for name in sorted(_declared()):
+        assert hasattr(L, name), name
+    assert set(m.EXPORTS) <= _declared()
+
+
+def test_strerror_names_every_code():
+    import paper_2001_11433_amd as m
+    L = m.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        s = L.mce_strerror(code).decode()
+        assert s and s != "unknown error"
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    import paper_2001_11433_amd as m
+    L = m.lib()
+    assert L.mce_static(None, 0, None, None, None, None) == m.MCE_EINVAL
+    assert L.mce_rank_metric(None, 0, None, None) == m.MCE_EINVAL
+
+
+def test_oracle_and_library_share_no_code():
+    # the two sides never import or include each other
+    for path in glob.glob(os.path.join(ROOT, "paper_2001_11433_amd", "**", "*"), recursive=True):
+        if os.path.isfile(path) and path.endswith((".py", ".hip", ".h", ".cpp")):
+            txt = open(path).read()
+            assert "oracle" not in re.findall(r"(?:import|include)\s+[\"<]?(\w+)", txt), path
+    for path in glob.glob(os.path.join(ROOT, "oracle", "*")):
+        if path.endswith((".py", ".cpp")):
+            txt = open(path).read()
+            assert "paper_2001_11433_amd" not in txt, path
