@@ -95,9 +95,16 @@ typedef struct {
   uint64_t donated;     /* subtrees handed to idle waves */
   uint64_t subproblems; /* subproblems that needed a search (|cand| > 0) */
   uint64_t max_cand;    /* largest |cand| of a subproblem */
+  uint64_t alg_ops;     /* algorithmic 32-bit integer operations of the search: per node
+                           3*s*ceil(|cand|/32) + 2*s + 2*|ext|*ceil(s/32), s = |cand u fini| */
   double rank_ms, build_ms, enum_ms; /* device time of ranking, subproblem build + queue, enumeration */
   uint32_t retries;     /* enumeration restarts after a DFS stack overflow */
   uint32_t pad;
+  /* diagnostics of the enumeration kernel: [0] re-based nodes, [1] nodes
+     searched in compact form, [2..5] shader clock cycles summed over waves
+     spent in wide nodes, re-basing, compact nodes and waiting for work, [6]
+     cycles spent donating, [7] (tasks << 32) | donation attempts */
+  uint64_t diag[8];
 } mce_result;
 
 /* Clique output in CSR form: clique i is vert[off[i] .. off[i+1]), vertices

@@ -46,8 +46,8 @@ class _Opts(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("set_hash", ctypes.c_uint64), ("nodes_total", ctypes.c_uint64),
                 ("donated", ctypes.c_uint64), ("subproblems", ctypes.c_uint64), ("max_cand", ctypes.c_uint64),
-                ("rank_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("enum_ms", ctypes.c_double),
-                ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("alg_ops", ctypes.c_uint64), ("rank_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("enum_ms", ctypes.c_double),
+                ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("diag", ctypes.c_uint64 * 8)]
 
 
 class _CliqueBuf(ctypes.Structure):
@@ -214,7 +214,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     else:
         _check(lib().mce_static(ctypes.byref(csr), RANKS[rank], ctypes.byref(o), ctypes.byref(res), None,
                                 ctypes.byref(pv) if pv else None))
-    out.update({k: getattr(res, k) for k, _ in _Result._fields_ if k != "pad"})
+    out.update({k: getattr(res, k) for k, _ in _Result._fields_ if k not in ("pad", "diag")})
+    out["diag"] = list(res.diag)
     if per_vertex:
         for k, t in tensors.items():
             out[k] = t[:dg.n]

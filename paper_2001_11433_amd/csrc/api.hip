@@ -27,38 +27,12 @@ void set_error(const char* fmt, ...) {
 
 namespace {
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  int ensure(size_t b) {
-    if (b <= bytes && p) return MCE_OK;
-    if (p) {
-      (void)hipFree(p);
-      p = nullptr;
-      bytes = 0;
-    }
-    size_t want = std::max<size_t>(b, 256);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
-      return e == hipErrorOutOfMemory ? MCE_ENOMEM : MCE_EDEVICE;
-    }
-    bytes = want;
-    return MCE_OK;
-  }
-  template <class T>
-  T* as() const {
-    return (T*)p;
-  }
-};
-
 // Device workspace of the static pipeline; grown on demand, reused across
 // calls on the same device, guarded by one mutex per device.
 struct Workspace {
   DevBuf rp, col, metric, tri, core, coredeg, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
-      gids, keys, vals, keys2, vals2, queue, ctl, pool, stacks, iota, clq_off, clq_vert, bad;
+      gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad;
+  EnumWork ew;
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
   void* sort_tmp = nullptr;
@@ -205,6 +179,74 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
   return MCE_EINVAL;
 }
 
+}  // namespace
+
+int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* retries) {
+  const mce_opts& opts = *j.opts;
+  const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
+  const uint32_t grid = (uint32_t)cu_count() * wpc;
+  uint32_t frame_cap = opts.frame_cap ? opts.frame_cap : 128;
+  frame_cap = std::min<uint32_t>(frame_cap, (uint32_t)j.max_p + 2);
+  frame_cap = std::max<uint32_t>(frame_cap, 2);
+  const uint64_t max_tickets = std::max<uint64_t>(1u << 24, 4 * j.nq);
+  const uint64_t qcap = j.nq + max_tickets;
+  const uint64_t pool_blocks = 1ULL << 16;  // 64 Ki records of 8 KiB, recycled
+  MCE_TRY(w.queue.ensure(qcap * sizeof(uint64_t)));
+  MCE_TRY(w.pool.ensure(pool_blocks * kBlockWords * sizeof(uint64_t)));
+  MCE_TRY(w.pool_next.ensure(pool_blocks * sizeof(uint32_t)));
+  MCE_TRY(w.ctl.ensure(CTL_WORDS * sizeof(uint64_t)));
+  if (retries) *retries = 0;
+  for (uint32_t attempt = 0;; ++attempt) {
+    const uint64_t stack_words = (uint64_t)frame_cap * std::max<uint64_t>(j.max_frame + 1, 8);
+    MCE_TRY(w.stacks.ensure((uint64_t)grid * stack_words * sizeof(uint64_t)));
+    MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap * sizeof(uint64_t), s));
+    MCE_TRY_HIP(launch_queue_fill(j.nq, j.order, w.queue.as<uint64_t>(), s));
+    std::memset(ctl, 0, CTL_WORDS * sizeof(uint64_t));
+    ctl[CTL_TAIL] = j.nq;
+    ctl[CTL_PENDING] = j.nq;
+    ctl[CTL_FREE] = 0;  // tag 0, first block 0
+    MCE_TRY_HIP(launch_pool_init(w.pool_next.as<uint32_t>(), pool_blocks, s));
+    MCE_TRY_HIP(hipMemcpyAsync(w.ctl.p, ctl, CTL_WORDS * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if (j.before_launch) MCE_TRY(j.before_launch(attempt, w.ctl.as<uint64_t>()));
+    EnumArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sub = j.sub;
+    a.arena = j.arena;
+    a.gids = j.gids;
+    a.queue = w.queue.as<uint64_t>();
+    a.qcap = qcap;
+    a.ctl = w.ctl.as<uint64_t>();
+    a.pool = w.pool.as<uint64_t>();
+    a.pool_next = w.pool_next.as<uint32_t>();
+    a.pool_blocks = pool_blocks;
+    a.max_tickets = max_tickets;
+    a.stacks = w.stacks.as<uint64_t>();
+    a.stack_words = stack_words;
+    a.frame_cap = frame_cap;
+    a.frame_words = (uint32_t)j.max_frame + 1;
+    a.donate_interval = opts.donate_interval ? opts.donate_interval : 256;
+    a.nodes_v = j.nodes_v;
+    a.count_v = j.count_v;
+    a.hash_v = j.hash_v;
+    a.cl_off = j.cl_off;
+    a.cl_vert = j.cl_vert;
+    a.cap_cliques = j.cap_cliques;
+    a.cap_verts = j.cap_verts;
+    if (j.nq > 0) MCE_TRY_HIP(launch_enum(a, grid, j.excl, s));
+    MCE_TRY_HIP(hipMemcpyAsync(ctl, w.ctl.p, CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    if (!(ctl[CTL_FLAGS] & 1ULL)) return MCE_OK;
+    if (frame_cap >= j.max_p + 2 || attempt >= 12) {
+      set_error("DFS stack overflow at %u frames", frame_cap);
+      return MCE_ENOMEM;
+    }
+    frame_cap = std::min<uint32_t>(frame_cap * 2, (uint32_t)j.max_p + 2);
+    if (retries) *retries = attempt + 1;
+  }
+}
+
+namespace {
+
 int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_result* out, mce_clique_buf* cl,
                 const mce_per_vertex* pv, Workspace& ws) {
   hipStream_t s = (hipStream_t)opts.hip_stream;
@@ -331,9 +373,6 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   uint32_t* svals;
   MCE_TRY(device_sort_desc(ws.keys.as<uint64_t>(), ws.vals.as<uint32_t>(), ws.keys2.as<uint64_t>(),
                            ws.vals2.as<uint32_t>(), n, ws.sort_tmp, ws.sort_bytes, s, &skeys, &svals));
-  const uint64_t max_tickets = std::max<uint64_t>(1u << 20, 4 * nq);
-  const uint64_t qcap = nq + max_tickets;
-  MCE_TRY(ws.queue.ensure(qcap * sizeof(uint64_t)));
   MCE_TRY(ws.iota.ensure(n * sizeof(uint32_t)));
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ws.iota.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
@@ -355,78 +394,52 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   }
 
   // --- persistent enumeration, restarted with deeper stacks on overflow
-  const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
-  const uint32_t grid = (uint32_t)cu_count() * wpc;
-  uint32_t frame_cap = opts.frame_cap ? opts.frame_cap : 128;
-  frame_cap = std::min<uint32_t>(frame_cap, (uint32_t)max_p + 2);
-  const uint64_t pool_cap = 1ULL << 26;  // 512 MiB of task records
-  MCE_TRY(ws.pool.ensure(pool_cap * sizeof(uint64_t)));
-  MCE_TRY(ws.ctl.ensure(CTL_WORDS * sizeof(uint64_t)));
-  uint64_t ctl[CTL_WORDS];
-  for (uint32_t attempt = 0;; ++attempt) {
+  EnumJob job;
+  job.sub.off = ws.off.as<uint64_t>();
+  job.sub.goff = ws.goff.as<uint64_t>();
+  job.sub.p = b.p;
+  job.sub.x = b.x;
+  job.sub.r0 = ws.iota.as<uint32_t>();
+  job.sub.r1 = ws.iota.as<uint32_t>();
+  job.arena = ws.arena.as<uint64_t>();
+  job.gids = ws.gids.as<uint32_t>();
+  job.nq = nq;
+  job.order = svals;
+  job.max_p = max_p;
+  job.max_frame = max_frame;
+  job.excl = false;
+  job.nodes_v = nodes_v;
+  job.count_v = count_v;
+  job.hash_v = hash_v;
+  job.cl_off = cl_off;
+  job.cl_vert = cl_vert;
+  job.cap_cliques = cl ? cl->cap_cliques : 0;
+  job.cap_verts = cl ? cl->cap_verts : 0;
+  job.opts = &opts;
+  job.before_launch = [&](uint32_t attempt, uint64_t* ctl_dev) -> int {
     if (attempt > 0) {
       // results of the aborted run are discarded: reset per-vertex outputs
       MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
       MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
     }
-    const uint64_t stack_words = (uint64_t)frame_cap * std::max<uint64_t>(max_frame + 1, 8);
-    MCE_TRY(ws.stacks.ensure((uint64_t)grid * stack_words * sizeof(uint64_t)));
-    MCE_TRY_HIP(hipMemsetAsync(ws.queue.p, 0, qcap * sizeof(uint64_t), s));
-    MCE_TRY_HIP(launch_queue_fill(nq, svals, ws.queue.as<uint64_t>(), s));
-    std::memset(ctl, 0, sizeof(ctl));
-    ctl[CTL_TAIL] = nq;
-    ctl[CTL_PENDING] = nq;
-    MCE_TRY_HIP(hipMemcpyAsync(ws.ctl.p, ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
     if (cl) {
-      hipLaunchKernelGGL(k_emit_isolated, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, ws.ctl.as<uint64_t>(),
-                         cl_off, cl_vert, cl->cap_cliques, cl->cap_verts);
+      hipLaunchKernelGGL(k_emit_isolated, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, ctl_dev, cl_off,
+                         cl_vert, cl->cap_cliques, cl->cap_verts);
       MCE_TRY_HIP(hipGetLastError());
     }
-    EnumArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.sub.off = ws.off.as<uint64_t>();
-    a.sub.goff = ws.goff.as<uint64_t>();
-    a.sub.p = b.p;
-    a.sub.x = b.x;
-    a.sub.r0 = ws.iota.as<uint32_t>();
-    a.sub.r1 = ws.iota.as<uint32_t>();
-    a.arena = ws.arena.as<uint64_t>();
-    a.gids = ws.gids.as<uint32_t>();
-    a.queue = ws.queue.as<uint64_t>();
-    a.qcap = qcap;
-    a.ctl = ws.ctl.as<uint64_t>();
-    a.pool = ws.pool.as<uint64_t>();
-    a.pool_cap = pool_cap;
-    a.max_tickets = max_tickets;
-    a.stacks = ws.stacks.as<uint64_t>();
-    a.stack_words = stack_words;
-    a.frame_cap = frame_cap;
-    a.frame_words = (uint32_t)max_frame + 1;
-    a.donate_interval = opts.donate_interval ? opts.donate_interval : 32;
-    a.nodes_v = nodes_v;
-    a.count_v = count_v;
-    a.hash_v = hash_v;
-    a.cl_off = cl_off;
-    a.cl_vert = cl_vert;
-    a.cap_cliques = cl ? cl->cap_cliques : 0;
-    a.cap_verts = cl ? cl->cap_verts : 0;
-    if (nq > 0) MCE_TRY_HIP(launch_enum(a, grid, false, s));
-    MCE_TRY_HIP(hipEventRecord(tm.e[3], s));
-    MCE_TRY_HIP(hipMemcpyAsync(ctl, ws.ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, s));
-    MCE_TRY_HIP(hipMemcpyAsync(stats, b.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
-    MCE_TRY_HIP(hipStreamSynchronize(s));
-    if (!(ctl[CTL_FLAGS] & 1ULL)) break;
-    if (frame_cap >= max_p + 2 || attempt >= 12) {
-      set_error("DFS stack overflow at %u frames", frame_cap);
-      return MCE_ENOMEM;
-    }
-    frame_cap = std::min<uint32_t>(frame_cap * 2, (uint32_t)max_p + 2);
-    out->retries = attempt + 1;
-  }
+    return MCE_OK;
+  };
+  uint64_t ctl[CTL_WORDS];
+  MCE_TRY(run_enum(job, ws.ew, s, ctl, &out->retries));
+  MCE_TRY_HIP(hipEventRecord(tm.e[3], s));
+  MCE_TRY_HIP(hipMemcpyAsync(stats, b.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
   out->count = stats[3] + ctl[CTL_COUNT];
   out->set_hash = stats[4] + ctl[CTL_HASH];
   out->nodes_total = stats[5] + ctl[CTL_NODES];
   out->donated = ctl[CTL_DONATED];
+  out->alg_ops = ctl[CTL_OPS];
+  for (int k = 0; k < 8; ++k) out->diag[k] = ctl[CTL_DIAG + k];
   out->rank_ms = tm.ms(0, 1);
   out->build_ms = tm.ms(1, 2);
   out->enum_ms = tm.ms(2, 3);

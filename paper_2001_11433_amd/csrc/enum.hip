@@ -2,32 +2,32 @@
 // bitset subproblems, one wavefront per task, tasks pulled from a global
 // atomic queue.
 //
-// A task is either the root of a subproblem (Algorithm 4: K = {v},
-// cand = the p higher-rank neighbours, fini = the rest) or a donated
-// continuation: a search node whose pivot and ext were already computed,
-// together with the not yet visited part of ext.  Donation is the unrolled
+// A task is the root of a subproblem (Algorithm 4: K = {v}, cand = the p
+// higher-rank neighbours, fini = the rest; or an edge subproblem of
+// Algorithm 5) or a donated continuation: a search node whose pivot and ext
+// are known, with the not yet visited part of ext.  Donation is the unrolled
 // child formula of Algorithm 3: child i of a node only needs
-// cand \ ext[1..i-1] and fini u ext[1..i-1], which is exactly the node's
-// (cand, fini) after its first i-1 children, so a suffix of ext can be handed
-// to another wave without changing the recursion tree (node counts match a
-// sequential run).
+// cand \ ext[1..i-1] and fini u ext[1..i-1], which is the node's (cand, fini)
+// after its first i-1 children, so a suffix of ext can be handed to another
+// wave without changing the recursion tree (node counts match a sequential
+// run).
 //
-// Search state of a node (one "frame"), in 64-bit words:
-//   P    [wp]  cand, over the local cand indices 0..p-1
-//   Xp   [wp]  the part of fini that came from cand (earlier siblings)
-//   ext  [wp]  children not yet visited
-//   Fb   [wf]  edge subproblems only: vertices whose addition would complete an
-//              excluded edge (Algorithms 6 and 8)
-//   Xx   [wx]  the part of fini from the subproblem's root fini
-//   z    [1]   sum of mix(id) over K (for the clique hash)
-//   q    [1]   the local vertex added to reach this node
-// Lane k of the wave holds word k of P, Xp, ext and Fb in registers (p <=
-// 4096, so wp <= 64).  Frames live in LDS when the subproblem's deepest
-// possible stack fits, else in a per-wave global region.
+// Two representations of a search node:
+//  * wide: bitsets over the subproblem's local indices (cand 0..p-1, then the
+//    relevant fini vertices), rows in the global arena, lane k holding word k
+//    of P (cand), Xp (fini from cand) and ext; Xx (fini from the root fini)
+//    lives in the frame.  Frames sit in LDS when the deepest possible stack
+//    fits, else in a per-wave global region.
+//  * compact: once a node has |cand| <= 64 and at most 64 fini vertices with a
+//    neighbour in cand, its subtree is re-based onto a 64 + 64 vertex
+//    universe.  Fini vertices with no neighbour in cand never enter a child's
+//    fini and can only tie as pivot when every t_u is 0, where ext = cand for
+//    any pivot, so dropping them changes neither cliques nor the recursion
+//    tree.  Lane l holds the compact rows of cand vertex l and fini vertex l
+//    (64-bit words) in VGPRs; P, Xp, Xx, ext are wave-uniform 64-bit words.
 //
-// Pivot (Algorithm 2): lanes take the candidate rows u in P u X, 64 at a
-// time, and compute t_u = sum_j popcount(P[j] & row_u[j]); a wave max over
-// (t_u, ~id(u)) picks the largest t_u, smallest id on ties.
+// Pivot (Algorithm 2): t_u = popcount(P & row_u) for every u in P u X in
+// parallel, then a wave max over (t_u, smallest id) picks the pivot.
 
 #include "dev.h"
 #include "internal.h"
@@ -36,100 +36,753 @@ namespace mce {
 
 namespace {
 
-constexpr uint32_t kKMax = 1024;     // largest materialised clique
-constexpr uint32_t kLdsWords = 1536; // per-wave LDS stack: 12 KiB
+constexpr uint32_t kKMax = 512;       // largest clique (|K| bound of the K list)
+constexpr uint32_t kLdsWords = 1024;  // per-wave LDS stack of the wide path: 8 KiB
+constexpr uint32_t kCF = 8;           // words per compact frame
+constexpr uint32_t kCFrames = 66;     // compact depth <= 64 below the re-based node
 
-struct Task {
-  uint32_t s;     // subproblem
-  uint32_t base;  // depth of the task's first frame
-  bool cont;
-  const uint64_t* rec;
+// pool record layout (64-bit words)
+enum { R_S = 0, R_TYPE = 1, R_DEPTH = 2, R_KLEN = 3, R_HDR = 4 };
+// compact record: frame at [4, 10), then rows and tables
+constexpr uint32_t kCR_PP = 10, kCR_XP = 74, kCR_PX = 138, kCR_EX = 202, kCR_KEY = 266, kCR_GP = 330, kCR_K = 362;
+
+struct Lds {
+  uint64_t sP[64];
+  uint64_t cstk[kCFrames * kCF];
+  uint32_t kG[kKMax];  // ids of K, roots first
+  uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
 };
 
+struct Acc {
+  uint64_t tn, tc, th, tops;
+};
+
+// Per-wave diagnostic counters (see mce_result.diag).
+struct Diag {
+  uint64_t rebases, cnodes, t_rebase, t_compact, t_idle, t_donate, attempts, tasks;
+};
+
+__device__ __forceinline__ uint64_t now() { return __builtin_readcyclecounter(); }
+
+struct Compact {
+  uint64_t rowPP, rowXP, rowPX, rowEx, zP;
+  uint32_t keyP, keyX, gP;
+  uint32_t np, nx;
+};
+
+// Claims the next queue slot and waits until it is filled or all work is
+// done.  The wait polls with relaxed (coherent) loads: an acquire at agent
+// scope invalidates the whole L2 of the XCD, which idle waves must not do
+// while others compute.  One acquire fence follows a successful claim, so the
+// task record written before the slot was published is visible.
 __device__ uint64_t claim_task(const EnumArgs& a) {
   uint64_t idx = fetch_add(&a.ctl[CTL_HEAD], 1);
   if (idx >= a.qcap) return 0;
   for (;;) {
-    uint64_t v = ld_acquire(&a.queue[idx]);
-    if (v) return v;
-    if (ld_acquire(&a.ctl[CTL_PENDING]) == 0) return 0;
+    uint64_t v = ld_relaxed(&a.queue[idx]);
+    if (v) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return v;
+    }
+    if (ld_relaxed(&a.ctl[CTL_PENDING]) == 0) return 0;
     __builtin_amdgcn_s_sleep(8);
   }
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_max(uint32_t v) {
+  uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+  return v > o ? v : o;
+}
+
+// Max over the 64 lanes: prefix max within rows of 16 (row_shr 1, 2, 4, 8),
+// then across rows (row_bcast 15, row_bcast 31); lane 63 holds the result.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = dpp_max<0x111, 0xF>(v);
+  v = dpp_max<0x112, 0xF>(v);
+  v = dpp_max<0x114, 0xF>(v);
+  v = dpp_max<0x118, 0xF>(v);
+  v = dpp_max<0x142, 0xA>(v);
+  v = dpp_max<0x143, 0xC>(v);
+  return readlane32(v, 63);
+}
+
+// Waves waiting for work (claims beyond the filled queue), at most 4.
+__device__ uint32_t idle_waves(const EnumArgs& a) {
+  uint64_t h = 0, tl = 0;
+  if (lane_id() == 0) {
+    h = ld_relaxed(&a.ctl[CTL_HEAD]);
+    tl = ld_relaxed(&a.ctl[CTL_TAIL]);
+  }
+  h = readlane64(h, 0);
+  tl = readlane64(tl, 0);
+  return h > tl ? (uint32_t)(h - tl < 4 ? h - tl : 4) : 0u;
+}
+
+__device__ bool starving(const EnumArgs& a) {
+  uint64_t h = 0, tl = 0;
+  if (lane_id() == 0) {
+    h = ld_relaxed(&a.ctl[CTL_HEAD]);
+    tl = ld_relaxed(&a.ctl[CTL_TAIL]);
+  }
+  return readlane64(h, 0) > readlane64(tl, 0);
+}
+
+constexpr uint32_t kNil = 0xFFFFFFFFu;
+
+// Donated-task records live in fixed blocks of a pool with a lock-free free
+// list (head = (tag << 32) | block, the tag defeats ABA).  A receiver copies
+// its record out and returns the block at once, so the pool recycles.
+__device__ uint32_t pool_pop(const EnumArgs& a) {
+  for (int tries = 0; tries < 64; ++tries) {
+    uint64_t old = ld_relaxed(&a.ctl[CTL_FREE]);
+    const uint32_t idx = (uint32_t)old;
+    if (idx == kNil) return kNil;
+    const uint32_t nxt = __hip_atomic_load(&a.pool_next[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t nw = (((old >> 32) + 1) << 32) | nxt;
+    if (__hip_atomic_compare_exchange_strong(&a.ctl[CTL_FREE], &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return idx;
+  }
+  return kNil;
+}
+
+// The caller has finished reading the block: a local wait for its loads is
+// all the ordering a reuse needs (the next owner only writes the block).
+__device__ void pool_push(const EnumArgs& a, uint32_t idx) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  for (;;) {
+    uint64_t old = ld_relaxed(&a.ctl[CTL_FREE]);
+    __hip_atomic_store(&a.pool_next[idx], (uint32_t)old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t nw = (((old >> 32) + 1) << 32) | idx;
+    if (__hip_atomic_compare_exchange_strong(&a.ctl[CTL_FREE], &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return;
+  }
+}
+
+// A queue ticket and a pool block for one donation (kNil: not now).
+__device__ uint32_t reserve_record(const EnumArgs& a, bool& can_donate) {
+  uint32_t blk = kNil;
+  uint32_t out_of_tickets = 0;
+  if (lane_id() == 0) {
+    blk = pool_pop(a);
+    if (blk != kNil) {
+      uint64_t tk = fetch_add(&a.ctl[CTL_TICKETS], 1);
+      if (tk >= a.max_tickets) {
+        pool_push(a, blk);
+        blk = kNil;
+        out_of_tickets = 1;
+      }
+    }
+  }
+  if (readlane32(out_of_tickets, 0)) can_donate = false;
+  return readlane32(blk, 0);
+}
+
+// Makes the record (plain stores of all lanes) visible at agent scope with
+// one release fence, then fills a queue slot.  `pending` is raised before the
+// slot is filled, and a task's own decrement comes after its donations in the
+// same counter's modification order, so pending reaches zero only when no
+// task is queued or running.
+__device__ void publish_record(const EnumArgs& a, uint32_t blk) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (lane_id() == 0) {
+    fetch_add(&a.ctl[CTL_PENDING], 1);
+    uint64_t slot = fetch_add(&a.ctl[CTL_TAIL], 1);
+    __hip_atomic_store(&a.queue[slot], (uint64_t)((1ULL << 63) | blk), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    fetch_add(&a.ctl[CTL_DONATED], 1);
+  }
+}
+
+// The wide frames [base, top) of the current task, whose unvisited children
+// can be donated while the wave works deeper (also from the compact path).
+struct WideCtx {
+  uint64_t* stk;
+  uint32_t F, wp, base, top, s, kroot;
+};
+
+// Hands the second half of the shallowest wide frame's unvisited children to
+// an idle wave.  Returns true if a record was queued.
+__device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& can_donate) {
+  const int lane = lane_id();
+  const uint32_t O_XP = w.wp, O_EXT = 2 * w.wp;
+  uint32_t i = w.base;
+  uint64_t e = 0;
+  for (; i < w.top; ++i) {
+    e = lane < (int)w.wp ? w.stk[(uint64_t)i * w.F + O_EXT + lane] : 0;
+    if (ballot(e != 0)) break;
+  }
+  if (i >= w.top) return false;
+  const uint32_t klen = w.kroot + i;
+  const uint64_t size = R_HDR + w.F + (klen + 1) / 2;
+  if (size > kBlockWords) return false;
+  const uint32_t cc = (uint32_t)__popcll(e);
+  const uint32_t incl = wave_incl_scan_u32(cc);
+  const uint32_t total = readlane32(incl, 63);
+  const uint32_t keep = total / 2;
+  const uint32_t before = incl - cc;
+  const uint32_t r = keep > before ? (keep - before < cc ? keep - before : cc) : 0;
+  uint64_t rest = e;
+  for (uint32_t z = 0; z < r; ++z) rest &= rest - 1;
+  const uint64_t km = e & ~rest;  // kept: the lowest `keep` children
+  const uint32_t blk = reserve_record(a, can_donate);
+  if (blk == kNil) return false;
+  uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
+  const uint64_t* fi = w.stk + (uint64_t)i * w.F;
+  if (lane == 0) {
+    rec[R_S] = w.s;
+    rec[R_TYPE] = 0;
+    rec[R_DEPTH] = i;
+    rec[R_KLEN] = klen;
+  }
+  // lane j owns word j of P, Xp and ext: P minus the kept children, Xp plus
+  // them, ext = the donated children
+  if (lane < (int)w.wp) {
+    rec[R_HDR + lane] = fi[lane] & ~km;
+    rec[R_HDR + O_XP + lane] = fi[O_XP + lane] | km;
+    rec[R_HDR + O_EXT + lane] = rest;
+  }
+  for (uint32_t k = 3 * w.wp + lane; k < w.F; k += kWave) rec[R_HDR + k] = fi[k];
+  for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + R_HDR + w.F))[j] = L.kG[j];
+  if (lane < (int)w.wp) w.stk[(uint64_t)i * w.F + O_EXT + lane] = km;
+  publish_record(a, blk);
+  __threadfence_block();
+  return true;
+}
+
+// K is maximal: count it, hash it, and optionally write it out.
+__device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, const uint32_t* kG) {
+  const int lane = lane_id();
+  ++acc.tc;
+  acc.th += clique_term(zsum, k);
+  if (!a.cl_vert) return;
+  uint64_t old = 0;
+  if (lane == 0) old = fetch_add(&a.ctl[CTL_CLQ], (1ULL << 32) | k);
+  old = readlane64(old, 0);
+  const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+  if (pos + k > 0xFFFFFFFFULL || k > kKMax) {
+    if (lane == 0) atomicOr((unsigned long long*)&a.ctl[CTL_FLAGS], 2ULL);
+    return;
+  }
+  if (id >= a.cap_cliques || pos + k > a.cap_verts) return;
+  for (uint32_t j = lane; j < k; j += kWave) {
+    uint32_t g = kG[j], r = 0;
+    for (uint32_t i = 0; i < k; ++i) r += kG[i] < g ? 1u : 0u;
+    a.cl_vert[pos + r] = g;
+  }
+  if (lane == 0) a.cl_off[id] = pos;
+}
+
+// --- compact path ------------------------------------------------------------
+
+template <bool EXCL>
+__device__ void compact_dfs(const EnumArgs& a, Lds& L, const Compact& c, uint32_t s, uint64_t P, uint64_t Xp,
+                            uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand, uint32_t kbase,
+                            uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since, const WideCtx* wide,
+                            Diag& dg) {
+  const int lane = lane_id();
+  uint32_t d = 0;
+  const uint64_t tn0 = acc.tn, t0 = now();
+  for (;;) {
+    bool pop = false;
+    if (expand) {
+      expand = false;
+      ++acc.tn;
+      if (P == 0) {
+        if ((Xp | Xx) == 0) emit(a, acc, zsum, kbase + d, L.kG);
+        pop = true;
+      } else {
+        const uint64_t mP = P | Xp;
+        const uint32_t k1 = ((mP >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP) : 0u;
+        const uint32_t k2 = ((Xx >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowXP) << 16) | c.keyX) : 0u;
+        const uint32_t mx = wave_max_u32(k1 > k2 ? k1 : k2);
+        const uint32_t row = mx & 0xFFu;
+        const uint64_t rpP = readlane64(c.rowPP, row & 63), rpX = readlane64(c.rowXP, row & 63);
+        ext = P & ~(row < 64 ? rpP : rpX);
+        const uint64_t sm = (uint64_t)__popcll(P) + __popcll(Xp) + __popcll(Xx);
+        acc.tops += 3ULL * sm * wv + 2ULL * (uint64_t)__popcll(ext) * wv + 2ULL * sm;
+      }
+    }
+    if (!pop && ext) {
+      const uint32_t q = (uint32_t)__builtin_ctzll(ext);
+      const uint64_t qb = 1ULL << q;
+      ext &= ext - 1;
+      if (EXCL && (F & qb)) {
+        // K u {q} would contain an excluded edge: q moves to fini unvisited
+        P &= ~qb;
+        Xp |= qb;
+        continue;
+      }
+      const uint64_t rq = readlane64(c.rowPP, q);
+      const uint64_t rqx = readlane64(c.rowPX, q);
+      P &= ~qb;
+      Xp |= qb;
+      {
+        const uint64_t v = lane == 0 ? P : lane == 1 ? Xp : lane == 2 ? Xx : lane == 3 ? ext : lane == 4 ? zsum : F;
+        if (lane < 6) L.cstk[d * kCF + lane] = v;
+      }
+      if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
+      P &= rq;
+      Xp &= rq;
+      Xx &= rqx;
+      if (EXCL) F |= readlane64(c.rowEx, q);
+      zsum += readlane64(c.zP, q);
+      ++d;
+      expand = true;
+
+      if (can_donate && ++since >= 4 * a.donate_interval) {
+        since = 0;
+        const uint64_t td = now();
+        for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
+          ++dg.attempts;
+          if (wide && donate_wide(a, L, *wide, can_donate)) continue;
+          uint32_t i = 0;
+          uint64_t e = 0;
+          for (; i < d; ++i) {
+            e = L.cstk[i * kCF + 3];
+            if (e) break;
+          }
+          const uint32_t klen = kbase + i;
+          if (i < d && kCR_K + (klen + 1) / 2 <= kBlockWords) {
+            const uint32_t keep = (uint32_t)__popcll(e) / 2;
+            uint64_t don = e;
+            for (uint32_t z = 0; z < keep; ++z) don &= don - 1;
+            const uint64_t km = e & ~don;  // the lowest `keep` children stay here
+            const uint32_t blk = reserve_record(a, can_donate);
+            if (blk != kNil) {
+              uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
+              if (lane == 0) {
+                rec[R_S] = s;
+                rec[R_TYPE] = 1;
+                rec[R_DEPTH] = c.np | (c.nx << 8);
+                rec[R_KLEN] = klen;
+              }
+              if (lane < 6) {
+                uint64_t v = L.cstk[i * kCF + lane];
+                if (lane == 0) v &= ~km;
+                if (lane == 1) v |= km;
+                if (lane == 3) v = don;
+                rec[R_HDR + lane] = v;
+              }
+              rec[kCR_PP + lane] = c.rowPP;
+              rec[kCR_XP + lane] = c.rowXP;
+              rec[kCR_PX + lane] = c.rowPX;
+              if (EXCL) rec[kCR_EX + lane] = c.rowEx;
+              rec[kCR_KEY + lane] = (uint64_t)c.keyP | ((uint64_t)c.keyX << 32);
+              ((uint32_t*)(rec + kCR_GP))[lane] = c.gP;
+              for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = L.kG[j];
+              if (lane == 0) L.cstk[i * kCF + 3] = km;
+              publish_record(a, blk);
+            } else {
+              break;
+            }
+          } else {
+            break;
+          }
+        }
+        dg.t_donate += now() - td;
+      }
+      continue;
+    }
+    // pop
+    if (d == 0) {
+      dg.cnodes += acc.tn - tn0;
+      dg.t_compact += now() - t0;
+      return;
+    }
+    --d;
+    const uint64_t v = lane < 6 ? L.cstk[d * kCF + lane] : 0;
+    P = readlane64(v, 0);
+    Xp = readlane64(v, 1);
+    Xx = readlane64(v, 2);
+    ext = readlane64(v, 3);
+    zsum = readlane64(v, 4);
+    F = readlane64(v, 5);
+  }
+}
+
+// Tie-break keys: rank of each compact row's vertex id among all compact rows
+// (smaller id -> larger key), row index in the low byte.
+__device__ void compact_keys(Compact& c) {
+  const int lane = lane_id();
+  uint32_t rp = 0, rx = 0;
+  for (uint32_t j = 0; j < c.np; ++j) {
+    const uint32_t g = readlane32(c.gP, j);
+    rp += g < c.gP ? 1u : 0u;
+  }
+  uint32_t gX = c.keyX;  // caller stashes the fini ids here before ranking
+  for (uint32_t j = 0; j < c.np; ++j) {
+    const uint32_t g = readlane32(c.gP, j);
+    rx += g < gX ? 1u : 0u;
+  }
+  for (uint32_t j = 0; j < c.nx; ++j) {
+    const uint32_t g = readlane32(gX, j);
+    rp += g < c.gP ? 1u : 0u;
+    rx += g < gX ? 1u : 0u;
+  }
+  c.keyP = lane < (int)c.np ? (((255u - rp) << 8) | (uint32_t)lane) : 0u;
+  c.keyX = lane < (int)c.nx ? (((255u - rx) << 8) | (64u + (uint32_t)lane)) : 0u;
+  c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
+}
+
+template <bool EXCL>
+__device__ void compact_from_record(const uint64_t* rec, Compact& c, Lds& L, uint64_t& P, uint64_t& Xp,
+                                    uint64_t& Xx, uint64_t& ext, uint64_t& zsum, uint64_t& F, uint32_t& klen) {
+  const int lane = lane_id();
+  const uint64_t hdr = readlane64(rec[R_DEPTH], 0);
+  c.np = (uint32_t)(hdr & 0xFF);
+  c.nx = (uint32_t)((hdr >> 8) & 0xFF);
+  klen = (uint32_t)readlane64(rec[R_KLEN], 0);
+  c.rowPP = rec[kCR_PP + lane];
+  c.rowXP = rec[kCR_XP + lane];
+  c.rowPX = rec[kCR_PX + lane];
+  c.rowEx = EXCL ? rec[kCR_EX + lane] : 0;
+  const uint64_t key = rec[kCR_KEY + lane];
+  c.keyP = (uint32_t)key;
+  c.keyX = (uint32_t)(key >> 32);
+  c.gP = ((const uint32_t*)(rec + kCR_GP))[lane];
+  c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
+  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
+  const uint64_t v = lane < 6 ? rec[R_HDR + lane] : 0;
+  P = readlane64(v, 0);
+  Xp = readlane64(v, 1);
+  Xx = readlane64(v, 2);
+  ext = readlane64(v, 3);
+  zsum = readlane64(v, 4);
+  F = readlane64(v, 5);
+}
+
+// --- the kernel ---------------------------------------------------------------
+
 template <bool EXCL>
 __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   extern __shared__ uint64_t lds_stack[];
-  __shared__ uint64_t sP[64];
-  __shared__ uint32_t sK[kKMax];
+  __shared__ Lds L;
   const int lane = threadIdx.x;
   uint64_t* const gstk = a.stacks + (uint64_t)blockIdx.x * a.stack_words;
-  uint64_t tot_c = 0, tot_h = 0, tot_n = 0;
+  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
   bool can_donate = a.max_tickets > 0;
+  uint32_t since = 0;
+  Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
+  const uint64_t t_start = now();
 
   for (;;) {
     uint64_t ref = 0;
+    const uint64_t tw = now();
     if (lane == 0) ref = claim_task(a);
     ref = readlane64(ref, 0);
+    dg.t_idle += now() - tw;
     if (ref == 0) break;
+    ++dg.tasks;
 
-    Task t;
-    t.cont = (ref >> 63) != 0;
-    if (!t.cont) {
-      t.s = (uint32_t)(ref - 1);
-      t.base = 0;
-      t.rec = nullptr;
-    } else {
-      t.rec = a.pool + (ref & ~(1ULL << 63));
-      t.s = (uint32_t)readlane64(t.rec[0], 0);
-      t.base = (uint32_t)readlane64(t.rec[1], 0);
-    }
-    const uint32_t s = t.s;
+    const bool cont = (ref >> 63) != 0;
+    const uint32_t blk = cont ? (uint32_t)(ref & 0xFFFFFFFFULL) : kNil;
+    const uint64_t* rec = cont ? a.pool + (uint64_t)blk * kBlockWords : nullptr;
+    const uint32_t s = cont ? (uint32_t)readlane64(rec[R_S], 0) : (uint32_t)(ref - 1);
+    const uint32_t rtype = cont ? (uint32_t)readlane64(rec[R_TYPE], 0) : 0u;
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
-    const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
-    const uint32_t F = 3 * wp + wf + wx + 2;
-    const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp, O_XX = 3 * wp + wf, O_Z = O_XX + wx, O_Q = O_Z + 1;
-    const uint64_t nrow = (uint64_t)p + x;
-    const uint64_t* rowP = a.arena + readlane64(a.sub.off[s], 0);
-    const uint64_t* rowPX = rowP + (uint64_t)wp * nrow;
-    const uint64_t* excl = rowPX + (uint64_t)p * wx;
-    const uint64_t* F0 = excl + (uint64_t)p * wp;
-    const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
-    const uint32_t r0 = readlane32(a.sub.r0[s], 0);
-    const uint32_t r1 = EXCL ? readlane32(a.sub.r1[s], 0) : 0;
-    const uint32_t kroot = EXCL ? 2 : 1;
+    const uint32_t wv = (p + x + 31) / 32;  // subproblem universe in 32-bit words
+    Acc acc = {0, 0, 0, 0};
+    bool overflow = false;
 
-    // deepest absolute frame index is p (one cand vertex per level)
-    uint64_t* stk;
-    uint32_t cap;
-    if ((uint64_t)(p + 2) * F <= kLdsWords) {
-      stk = lds_stack;
-      cap = kLdsWords / F;
+    if (rtype == 1) {
+      // donated compact subtree
+      Compact c;
+      uint64_t P, Xp, Xx, ext, zsum, F;
+      uint32_t klen;
+      compact_from_record<EXCL>(rec, c, L, P, Xp, Xx, ext, zsum, F, klen);
+      __threadfence_block();
+      if (lane == 0) pool_push(a, blk);
+      compact_dfs<EXCL>(a, L, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since, nullptr, dg);
     } else {
-      stk = gstk;
-      cap = (uint32_t)(a.stack_words / F);
-    }
-    uint64_t tn = 0, tc = 0, th = 0;
-    bool overflow = t.base + 2 > cap;
+      const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
+      const uint32_t F = 3 * wp + wf + wx + 1;
+      const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp, O_XX = 3 * wp + wf, O_Z = O_XX + wx;
+      const uint64_t nrow = (uint64_t)p + x;
+      const uint64_t* rowP = a.arena + readlane64(a.sub.off[s], 0);
+      const uint64_t* rowPX = rowP + (uint64_t)wp * nrow;
+      const uint64_t* excl = rowPX + (uint64_t)p * wx;
+      const uint64_t* F0 = excl + (uint64_t)p * wp;
+      const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
+      const uint32_t kroot = EXCL ? 2 : 1;
 
-    uint64_t rP = 0, rXp = 0, rExt = 0, rF = 0, zsum = 0;
-    uint32_t d = t.base;
-    uint64_t* fr = stk + (uint64_t)d * F;
-    bool expand = false;
-    if (!overflow) {
-      if (!t.cont) {
-        rP = lane < (int)wp ? full_word(p, lane) : 0;
-        if (EXCL && lane < (int)wp) rF = F0[lane];
-        for (uint32_t k = lane; k < wx; k += kWave) fr[O_XX + k] = full_word(x, k);
-        zsum = mix64(r0) + (EXCL ? mix64(r1) : 0);
-        expand = true;
+      uint64_t* stk;
+      uint32_t cap;
+      if ((uint64_t)(p + 2) * F <= kLdsWords) {
+        stk = lds_stack;
+        cap = kLdsWords / F;
       } else {
-        const uint64_t* rf = t.rec + 2;
-        for (uint32_t k = lane; k < F; k += kWave) fr[k] = rf[k];
-        const uint32_t* rq = (const uint32_t*)(t.rec + 2 + F);
-        for (uint32_t i = lane; i + 1 < t.base; i += kWave) stk[(uint64_t)(i + 1) * F + O_Q] = rq[i];
+        stk = gstk;
+        cap = (uint32_t)(a.stack_words / F);
+      }
+      const uint32_t base = cont ? (uint32_t)readlane64(rec[R_DEPTH], 0) : 0u;
+      overflow = base + 2 > cap || base + kroot >= kKMax;
+
+      uint64_t rP = 0, rXp = 0, rExt = 0, rF = 0, zsum = 0;
+      uint32_t d = base;
+      uint64_t* fr = stk + (uint64_t)d * F;
+      bool expand = false;
+      if (!overflow) {
+        if (!cont) {
+          rP = lane < (int)wp ? full_word(p, lane) : 0;
+          if (EXCL && lane < (int)wp) rF = F0[lane];
+          for (uint32_t k = lane; k < wx; k += kWave) fr[O_XX + k] = full_word(x, k);
+          const uint32_t r0 = readlane32(a.sub.r0[s], 0);
+          zsum = mix64(r0);
+          if (lane == 0) L.kG[0] = r0;
+          if (EXCL) {
+            const uint32_t r1 = readlane32(a.sub.r1[s], 0);
+            zsum += mix64(r1);
+            if (lane == 0) L.kG[1] = r1;
+          }
+          expand = true;
+        } else {
+          const uint32_t klen = (uint32_t)readlane64(rec[R_KLEN], 0);
+          for (uint32_t k = lane; k < F; k += kWave) fr[k] = rec[R_HDR + k];
+          for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = ((const uint32_t*)(rec + R_HDR + F))[j];
+          __threadfence_block();
+          if (lane < (int)wp) {
+            rP = fr[lane];
+            rXp = fr[O_XP + lane];
+            rExt = fr[O_EXT + lane];
+            if (EXCL) rF = fr[O_FB + lane];
+          }
+          zsum = readlane64(fr[O_Z], 0);
+        }
+      }
+      if (cont) {
         __threadfence_block();
+        if (lane == 0) pool_push(a, blk);
+      }
+      WideCtx wctx;
+      wctx.stk = stk;
+      wctx.F = F;
+      wctx.wp = wp;
+      wctx.base = base;
+      wctx.top = base;
+      wctx.s = s;
+      wctx.kroot = kroot;
+
+      while (!overflow) {
+        bool do_pop = false;
+        if (expand) {
+          expand = false;
+          if (ballot(rP != 0) == 0) {
+            ++acc.tn;
+            // cand empty: K is maximal iff fini is empty too
+            bool xe = ballot(rXp != 0) == 0;
+            if (xe) {
+              bool nz = false;
+              for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
+              xe = ballot(nz) == 0;
+            }
+            if (xe) emit(a, acc, zsum, kroot + d, L.kG);
+            do_pop = true;
+          } else {
+            if (lane < (int)wp) L.sP[lane] = rP;
+            __syncthreads();
+            uint32_t p_cnt = 0;
+            for (uint32_t j = 0; j < wp; ++j) p_cnt += (uint32_t)__popcll(L.sP[j]);
+            // One pass over the rows of P u X: t_u for the pivot and, when
+            // |cand| <= 64, the fini vertices with a neighbour in cand (the
+            // vertices a re-based node keeps; give up beyond 64).
+            bool ok = p_cnt <= 64 && kroot + d + kCFrames <= kKMax;
+            uint32_t nx = 0;
+            uint64_t best = 0;
+            uint32_t bu = 0;
+            uint32_t s_mem = 0;
+            // one 64-row chunk: member mask M, fini members MX, first row u0
+            auto chunk = [&](uint64_t M, uint64_t MX, uint32_t u0) {
+              s_mem += (uint32_t)__popcll(M);
+              const uint32_t u = u0 + lane;
+              uint32_t tu = 0;
+              if ((M >> lane) & 1ULL) {
+                for (uint32_t j = 0; j < wp; ++j) tu += (uint32_t)__popcll(L.sP[j] & rowP[(uint64_t)j * nrow + u]);
+                const uint64_t key = ((uint64_t)tu << 32) | (0xFFFFFFFFu - gid[u]);
+                if (key > best) {
+                  best = key;
+                  bu = u;
+                }
+              }
+              if (ok) {
+                const bool keepx = ((MX >> lane) & 1ULL) && tu > 0;
+                const uint64_t b = ballot(keepx);
+                const uint32_t cnt = (uint32_t)__popcll(b);
+                if (nx + cnt > 64) {
+                  ok = false;
+                } else {
+                  if (keepx) L.xl[nx + mask_prefix(b, lane)] = u;
+                  nx += cnt;
+                }
+              }
+            };
+            const uint64_t mem = rP | rXp;
+            for (uint32_t k = 0; k < wp; ++k) {
+              const uint64_t M = readlane64(mem, k);
+              if (M) chunk(M, readlane64(rXp, k), k * 64);
+            }
+            // fini words of the root fini: loaded lane-parallel, only non-zero words visited
+            for (uint32_t kb = 0; kb < wx; kb += kWave) {
+              const uint64_t xw = kb + lane < wx ? fr[O_XX + kb + lane] : 0;
+              uint64_t nzm = ballot(xw != 0);
+              while (nzm) {
+                const uint32_t jj = (uint32_t)__builtin_ctzll(nzm);
+                nzm &= nzm - 1;
+                const uint64_t M = readlane64(xw, jj);
+                chunk(M, M, p + (kb + jj) * 64);
+              }
+            }
+            bool rebased = false;
+            if (ok) {
+                // re-base this node and search its subtree in compact form
+                const uint64_t tr = now();
+                ++dg.rebases;
+                Compact c;
+                c.np = p_cnt;
+                c.nx = nx;
+                uint32_t pm = 0;
+                {
+                  uint32_t j = 0;
+                  for (uint32_t k = 0; k < wp; ++k) {
+                    uint64_t m = readlane64(rP, k);
+                    while (m) {
+                      const uint32_t b = (uint32_t)__builtin_ctzll(m);
+                      if (lane == (int)j) pm = k * 64 + b;
+                      ++j;
+                      m &= m - 1;
+                    }
+                  }
+                }
+                __syncthreads();
+                const uint32_t ux = lane < (int)nx ? L.xl[lane] : 0;
+                uint64_t cPP = 0, cXP = 0, cEx = 0, cF = 0;
+                uint32_t cnt = 0;
+                for (uint32_t k = 0; k < wp; ++k) {
+                  uint64_t m = readlane64(rP, k);
+                  if (m == 0) continue;
+                  const uint64_t wP = lane < (int)c.np ? rowP[(uint64_t)k * nrow + pm] : 0;
+                  const uint64_t wX = lane < (int)nx ? rowP[(uint64_t)k * nrow + ux] : 0;
+                  const uint64_t wE = (EXCL && lane < (int)c.np) ? excl[(uint64_t)pm * wp + k] : 0;
+                  const uint64_t fk = EXCL ? readlane64(rF, k) : 0;
+                  while (m) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(m);
+                    cPP |= ((wP >> b) & 1ULL) << cnt;
+                    cXP |= ((wX >> b) & 1ULL) << cnt;
+                    if (EXCL) {
+                      cEx |= ((wE >> b) & 1ULL) << cnt;
+                      cF |= ((fk >> b) & 1ULL) << cnt;
+                    }
+                    ++cnt;
+                    m &= m - 1;
+                  }
+                }
+                c.rowPP = cPP;
+                c.rowXP = cXP;
+                c.rowEx = cEx;
+                // cand rows over the compact fini columns = transpose of cXP
+                uint64_t cPX = 0;
+                for (uint32_t j = 0; j < c.np; ++j) {
+                  const uint64_t col = ballot(lane < (int)nx && ((cXP >> j) & 1ULL));
+                  if (lane == (int)j) cPX = col;
+                }
+                c.rowPX = cPX;
+                c.gP = lane < (int)c.np ? gid[pm] : 0xFFFFFFFFu;
+                c.keyX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
+                compact_keys(c);
+                const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
+                const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
+                const uint64_t Fc = EXCL ? readlane64(cF, 0) : 0;
+                wctx.top = d;
+                dg.t_rebase += now() - tr;
+                compact_dfs<EXCL>(a, L, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc, can_donate,
+                                  since, &wctx, dg);
+                rebased = true;
+                do_pop = true;
+            }
+            if (!rebased) {
+              ++acc.tn;
+              // pivot: largest |P n Gamma(u)| over u in P u X, smallest id on ties
+              const uint64_t mx = wave_max_u64(best);
+              const int wl = __ffsll((unsigned long long)ballot(best == mx)) - 1;
+              const uint32_t piv = readlane32(bu, wl);
+              rExt = lane < (int)wp ? (rP & ~rowP[(uint64_t)lane * nrow + piv]) : 0;
+              const uint64_t n_ext = wave_sum_u64((uint64_t)__popcll(rExt));
+              acc.tops += 3ULL * s_mem * wv + 2ULL * n_ext * wv + 2ULL * s_mem;
+            }
+            __syncthreads();
+          }
+        }
+        if (!do_pop) {
+          const uint64_t m = ballot(rExt != 0);
+          if (m == 0) {
+            do_pop = true;
+          } else {
+            const int kq = __ffsll((unsigned long long)m) - 1;
+            const uint64_t w = readlane64(rExt, kq);
+            const int b = __ffsll((unsigned long long)w) - 1;
+            const uint32_t q = (uint32_t)kq * 64 + b;
+            const uint64_t qb = lane == kq ? (1ULL << b) : 0;
+            rExt &= ~qb;
+            if (EXCL && ((readlane64(rF, kq) >> b) & 1ULL)) {
+              // K u {q} would contain an excluded edge: q moves to fini unvisited
+              rP &= ~qb;
+              rXp |= qb;
+              continue;
+            }
+            if (d + 2 > cap || kroot + d + 1 >= kKMax) {
+              overflow = true;
+              break;
+            }
+            const uint64_t rq = lane < (int)wp ? rowP[(uint64_t)lane * nrow + q] : 0;
+            const uint64_t cP = rP & rq, cXp = rXp & rq;
+            rP &= ~qb;
+            rXp |= qb;
+            uint64_t* ch = fr + F;
+            if (lane < (int)wp) {
+              fr[lane] = rP;
+              fr[O_XP + lane] = rXp;
+              fr[O_EXT + lane] = rExt;
+              if (EXCL) fr[O_FB + lane] = rF;
+            }
+            for (uint32_t k = lane; k < wx; k += kWave) ch[O_XX + k] = fr[O_XX + k] & rowPX[(uint64_t)q * wx + k];
+            uint64_t cF = 0;
+            if (EXCL && lane < (int)wp) cF = rF | excl[(uint64_t)q * wp + lane];
+            const uint32_t gq = gid[q];
+            if (lane == 0) {
+              fr[O_Z] = zsum;
+              L.kG[kroot + d] = gq;
+            }
+            zsum += mix64(gq);
+            if (lane == 0) ch[O_Z] = zsum;
+            __threadfence_block();
+            fr = ch;
+            ++d;
+            rP = cP;
+            rXp = cXp;
+            rF = cF;
+            rExt = 0;
+            expand = true;
+
+            // hand the second half of the shallowest unvisited siblings to idle waves
+            if (can_donate && ++since >= a.donate_interval) {
+              since = 0;
+              const uint64_t td = now();
+              wctx.top = d;
+              if (starving(a)) {
+                ++dg.attempts;
+                donate_wide(a, L, wctx, can_donate);
+              }
+              dg.t_donate += now() - td;
+            }
+            continue;
+          }
+        }
+        // pop
+        if (d == base) break;
+        fr -= F;
+        --d;
         if (lane < (int)wp) {
           rP = fr[lane];
           rXp = fr[O_XP + lane];
@@ -139,243 +792,37 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
         zsum = readlane64(fr[O_Z], 0);
       }
     }
-    uint32_t since = 0;
-
-    while (!overflow) {
-      bool do_pop = false;
-      if (expand) {
-        expand = false;
-        ++tn;
-        if (ballot(rP != 0) == 0) {
-          // cand empty: K is maximal iff fini is empty too
-          bool xe = ballot(rXp != 0) == 0;
-          if (xe) {
-            bool nz = false;
-            for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
-            xe = ballot(nz) == 0;
-          }
-          if (xe) {
-            const uint32_t k = kroot + (d);
-            ++tc;
-            th += clique_term(zsum, k);
-            if (a.cl_vert) {
-              uint64_t old = 0;
-              if (lane == 0) old = fetch_add(&a.ctl[CTL_CLQ], (1ULL << 32) | k);
-              old = readlane64(old, 0);
-              const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
-              if (pos + k > 0xFFFFFFFFULL || k > kKMax) {
-                if (lane == 0) atomicOr((unsigned long long*)&a.ctl[CTL_FLAGS], 2ULL);
-              } else if (id < a.cap_cliques && pos + k <= a.cap_verts) {
-                if (lane == 0) {
-                  sK[0] = r0;
-                  if (EXCL) sK[1] = r1;
-                }
-                for (uint32_t i = lane + 1; i <= d; i += kWave)
-                  sK[kroot + i - 1] = gid[(uint32_t)stk[(uint64_t)i * F + O_Q]];
-                __syncthreads();
-                for (uint32_t j = lane; j < k; j += kWave) {
-                  uint32_t g = sK[j], r = 0;
-                  for (uint32_t i = 0; i < k; ++i) r += sK[i] < g ? 1u : 0u;
-                  a.cl_vert[pos + r] = g;
-                }
-                if (lane == 0) a.cl_off[id] = pos;
-                __syncthreads();
-              }
-            }
-          }
-          do_pop = true;
-        } else {
-          // pivot: argmax over u in P u X of |P n Gamma(u)|, smallest id on ties
-          if (lane < (int)wp) sP[lane] = rP;
-          __syncthreads();
-          uint64_t best = 0;
-          uint32_t bu = 0;
-          const uint64_t mem = rP | rXp;
-          for (uint32_t k = 0; k < wp; ++k) {
-            const uint64_t M = readlane64(mem, k);
-            if (M == 0) continue;
-            if ((M >> lane) & 1ULL) {
-              const uint32_t u = k * 64 + lane;
-              uint32_t tu = 0;
-              for (uint32_t j = 0; j < wp; ++j) tu += (uint32_t)__popcll(sP[j] & rowP[(uint64_t)j * nrow + u]);
-              const uint64_t key = ((uint64_t)tu << 32) | (0xFFFFFFFFu - gid[u]);
-              if (key > best) { best = key; bu = u; }
-            }
-          }
-          for (uint32_t k = 0; k < wx; ++k) {
-            const uint64_t M = fr[O_XX + k];
-            if (M == 0) continue;
-            if ((M >> lane) & 1ULL) {
-              const uint32_t u = p + k * 64 + lane;
-              uint32_t tu = 0;
-              for (uint32_t j = 0; j < wp; ++j) tu += (uint32_t)__popcll(sP[j] & rowP[(uint64_t)j * nrow + u]);
-              const uint64_t key = ((uint64_t)tu << 32) | (0xFFFFFFFFu - gid[u]);
-              if (key > best) { best = key; bu = u; }
-            }
-          }
-          const uint64_t mx = wave_max_u64(best);
-          const int wl = __ffsll((unsigned long long)ballot(best == mx)) - 1;
-          const uint32_t piv = readlane32(bu, wl);
-          rExt = lane < (int)wp ? (rP & ~rowP[(uint64_t)lane * nrow + piv]) : 0;
-          __syncthreads();
-        }
-      }
-      if (!do_pop) {
-        const uint64_t m = ballot(rExt != 0);
-        if (m == 0) {
-          do_pop = true;
-        } else {
-          const int kq = __ffsll((unsigned long long)m) - 1;
-          const uint64_t w = readlane64(rExt, kq);
-          const int b = __ffsll((unsigned long long)w) - 1;
-          const uint32_t q = (uint32_t)kq * 64 + b;
-          const uint64_t qb = lane == kq ? (1ULL << b) : 0;
-          rExt &= ~qb;
-          if (EXCL && ((readlane64(rF, kq) >> b) & 1ULL)) {
-            // K u {q} would contain an excluded edge: q moves to fini unvisited
-            rP &= ~qb;
-            rXp |= qb;
-            continue;
-          }
-          if (d + 2 > cap) {
-            overflow = true;
-            break;
-          }
-          const uint64_t rq = lane < (int)wp ? rowP[(uint64_t)lane * nrow + q] : 0;
-          const uint64_t cP = rP & rq, cXp = rXp & rq;
-          rP &= ~qb;
-          rXp |= qb;
-          uint64_t* ch = fr + F;
-          if (lane < (int)wp) {
-            fr[lane] = rP;
-            fr[O_XP + lane] = rXp;
-            fr[O_EXT + lane] = rExt;
-            if (EXCL) fr[O_FB + lane] = rF;
-          }
-          for (uint32_t k = lane; k < wx; k += kWave) ch[O_XX + k] = fr[O_XX + k] & rowPX[(uint64_t)q * wx + k];
-          uint64_t cF = 0;
-          if (EXCL && lane < (int)wp) cF = rF | excl[(uint64_t)q * wp + lane];
-          fr[O_Z] = zsum;  // (same value from every lane)
-          zsum += mix64(gid[q]);
-          if (lane == 0) {
-            ch[O_Z] = zsum;
-            ch[O_Q] = q;
-          }
-          __threadfence_block();
-          fr = ch;
-          ++d;
-          rP = cP;
-          rXp = cXp;
-          rF = cF;
-          rExt = 0;
-          expand = true;
-
-          // hand the second half of the shallowest unvisited siblings to idle waves
-          if (can_donate && ++since >= a.donate_interval) {
-            since = 0;
-            uint64_t h = 0, tl = 0;
-            if (lane == 0) {
-              h = ld_relaxed(&a.ctl[CTL_HEAD]);
-              tl = ld_relaxed(&a.ctl[CTL_TAIL]);
-            }
-            h = readlane64(h, 0);
-            tl = readlane64(tl, 0);
-            if (h > tl) {
-              uint32_t i = t.base;
-              uint64_t e = 0;
-              for (; i < d; ++i) {
-                e = lane < (int)wp ? stk[(uint64_t)i * F + O_EXT + lane] : 0;
-                if (ballot(e != 0)) break;
-              }
-              if (i < d) {
-                const uint32_t c = (uint32_t)__popcll(e);
-                const uint32_t incl = wave_incl_scan_u32(c);
-                const uint32_t total = readlane32(incl, 63);
-                const uint32_t keep = total / 2;
-                const uint32_t before = incl - c;
-                uint32_t r = keep > before ? (keep - before < c ? keep - before : c) : 0;
-                uint64_t rest = e;
-                for (uint32_t z = 0; z < r; ++z) rest &= rest - 1;
-                const uint64_t km = e & ~rest;  // kept: the lowest `keep` children
-                const uint64_t don = rest;
-                const uint64_t size = 2 + F + (i + 1) / 2;
-                uint64_t off = 0;
-                uint32_t ok = 0;
-                if (lane == 0) {
-                  uint64_t tk = fetch_add(&a.ctl[CTL_TICKETS], 1);
-                  if (tk < a.max_tickets) {
-                    off = fetch_add(&a.ctl[CTL_POOL], size);
-                    ok = off + size <= a.pool_cap;
-                  }
-                }
-                ok = readlane32(ok, 0);
-                off = readlane64(off, 0);
-                if (!ok) {
-                  can_donate = false;
-                } else {
-                  uint64_t* rec = a.pool + off;
-                  const uint64_t* fi = stk + (uint64_t)i * F;
-                  if (lane == 0) {
-                    rec[0] = s;
-                    rec[1] = i;
-                  }
-                  // lane j owns word j of P, Xp and ext: P minus the kept
-                  // children, Xp plus them, ext = the donated children
-                  if (lane < (int)wp) {
-                    rec[2 + lane] = fi[lane] & ~km;
-                    rec[2 + O_XP + lane] = fi[O_XP + lane] | km;
-                    rec[2 + O_EXT + lane] = don;
-                  }
-                  for (uint32_t k = 3 * wp + lane; k < F; k += kWave) rec[2 + k] = fi[k];
-                  uint32_t* rq = (uint32_t*)(rec + 2 + F);
-                  for (uint32_t j = lane; j + 1 < i; j += kWave) rq[j] = (uint32_t)stk[(uint64_t)(j + 1) * F + O_Q];
-                  if (lane < (int)wp) stk[(uint64_t)i * F + O_EXT + lane] = km;
-                  __threadfence();
-                  if (lane == 0) {
-                    fetch_add(&a.ctl[CTL_PENDING], 1);
-                    uint64_t slot = fetch_add(&a.ctl[CTL_TAIL], 1);
-                    st_release(&a.queue[slot], (uint64_t)((1ULL << 63) | off));
-                    fetch_add(&a.ctl[CTL_DONATED], 1);
-                  }
-                  __threadfence_block();
-                }
-              }
-            }
-          }
-          continue;
-        }
-      }
-      // pop
-      if (d == t.base) break;
-      fr -= F;
-      --d;
-      if (lane < (int)wp) {
-        rP = fr[lane];
-        rXp = fr[O_XP + lane];
-        rExt = fr[O_EXT + lane];
-        if (EXCL) rF = fr[O_FB + lane];
-      }
-      zsum = readlane64(fr[O_Z], 0);
-    }
 
     if (overflow) {
       if (lane == 0) atomicOr((unsigned long long*)&a.ctl[CTL_FLAGS], 1ULL);
     }
     if (lane == 0) {
-      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)tn);
-      if (a.count_v && tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)tc);
-      if (a.hash_v && th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)th);
-      __threadfence();
+      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
+      if (a.count_v && acc.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)acc.tc);
+      if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
       fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
     }
-    tot_n += tn;
-    tot_c += tc;
-    tot_h += th;
+    tot_n += acc.tn;
+    tot_c += acc.tc;
+    tot_h += acc.th;
+    tot_ops += acc.tops;
   }
   if (lane == 0) {
     if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
     if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
     if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
+    if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
+    const uint64_t t_all = now() - t_start;
+    // donation inside the compact path is also inside t_compact
+    const uint64_t t_wide = t_all - dg.t_idle - dg.t_rebase - dg.t_compact;
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 0], (unsigned long long)dg.rebases);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 1], (unsigned long long)dg.cnodes);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 2], (unsigned long long)t_wide);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 3], (unsigned long long)dg.t_rebase);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 4], (unsigned long long)dg.t_compact);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 5], (unsigned long long)dg.t_idle);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 6], (unsigned long long)dg.t_donate);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 7], (unsigned long long)((dg.tasks << 32) | (dg.attempts & 0xFFFFFFFFULL)));
   }
 }
 
@@ -389,6 +836,16 @@ hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStre
     hipLaunchKernelGGL(k_enum<true>, dim3(grid), dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL(k_enum<false>, dim3(grid), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_pool_init(uint32_t* next, uint64_t blocks) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < blocks) next[i] = i + 1 < blocks ? (uint32_t)(i + 1) : 0xFFFFFFFFu;
+}
+
+hipError_t launch_pool_init(uint32_t* next, uint64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_init, dim3((uint32_t)((blocks + 255) / 256)), dim3(256), 0, s, next, blocks);
   return hipGetLastError();
 }
 

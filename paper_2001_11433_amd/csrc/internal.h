@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <functional>
+
 #include "../../include/mce.h"
 
 namespace mce {
@@ -27,6 +30,7 @@ void set_error(const char* fmt, ...);
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxCand = 4096;  // |cand| per subproblem: 64 words of 64 bits
+constexpr uint32_t kBlockWords = 1024;  // one donated-task record
 
 // Control block of one enumeration launch (uint64 words).
 enum {
@@ -41,7 +45,10 @@ enum {
   CTL_COUNT = 8,     // maximal cliques
   CTL_HASH = 9,      // sum of clique hashes
   CTL_NODES = 10,    // search nodes
-  CTL_WORDS = 16
+  CTL_OPS = 11,      // algorithmic 32-bit integer operations
+  CTL_FREE = 12,     // free list of pool blocks: (tag << 32) | first free block
+  CTL_DIAG = 16,     // 8 diagnostic counters (see mce_result.diag)
+  CTL_WORDS = 24
 };
 
 // Per-subproblem tables, indexed by subproblem id.
@@ -61,8 +68,9 @@ struct EnumArgs {
   uint64_t* queue;
   uint64_t qcap;
   uint64_t* ctl;
-  uint64_t* pool;
-  uint64_t pool_cap;
+  uint64_t* pool;        // pool_blocks blocks of kBlockWords words (donated task records)
+  uint32_t* pool_next;   // free-list links
+  uint64_t pool_blocks;
   uint64_t max_tickets;
   uint64_t* stacks;
   uint64_t stack_words;  // per wave
@@ -77,6 +85,68 @@ struct EnumArgs {
   uint32_t* cl_vert;
   uint64_t cap_cliques, cap_verts;
 };
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t b) {
+    if (b <= bytes && p) return MCE_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t want = std::max<size_t>(b, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? MCE_ENOMEM : MCE_EDEVICE;
+    }
+    bytes = want;
+    return MCE_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+
+// Buffers of one persistent enumeration launch (queue, control block, task
+// pool, DFS stacks).  Each incremental state owns one, so sessions on
+// different streams never share them.
+struct EnumWork {
+  DevBuf queue, ctl, pool, pool_next, stacks;
+};
+
+// One persistent enumeration over a table of subproblems.
+struct EnumJob {
+  SubTab sub;
+  const uint64_t* arena;
+  const uint32_t* gids;
+  uint64_t nq;             // root tasks
+  const uint32_t* order;   // their subproblem ids, in queue order
+  uint64_t max_p, max_frame;
+  bool excl;               // edge subproblems with excluded edges
+  uint64_t *nodes_v, *count_v, *hash_v;
+  uint64_t* cl_off;
+  uint32_t* cl_vert;
+  uint64_t cap_cliques, cap_verts;
+  const mce_opts* opts;
+  std::function<int(uint32_t attempt, uint64_t* ctl_dev)> before_launch;
+};
+
+// Runs the job (restarting with deeper DFS stacks after an overflow) and
+// copies the control block to `ctl` (CTL_WORDS words).
+int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* retries);
 
 // rank.hip
 hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s);
@@ -116,5 +186,6 @@ int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_
 // enum.hip
 hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
 hipError_t launch_finish_offsets(uint64_t* off, uint64_t n_cliques, uint64_t n_verts, hipStream_t s);
+hipError_t launch_pool_init(uint32_t* next, uint64_t blocks, hipStream_t s);
 
 }  // namespace mce
