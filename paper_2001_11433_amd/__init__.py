@@ -246,3 +246,76 @@ def mce_features(g, stream=None):
 def to_u64(t) -> np.ndarray:
     """Device int64 tensor holding uint64 bits -> numpy uint64."""
     return t.detach().cpu().numpy().view(np.uint64)
+
+
+class ImceState:
+    """Device-resident incremental state (imce_create / imce_add_edges /
+    imce_destroy).  `add` returns a dict with the batch result and, on
+    request, the new and subsumed cliques as sorted lists of sorted tuples."""
+
+    def __init__(self, g, stream=None, waves_per_cu: int = 0, donate_interval: int = 0):
+        torch = _torch()
+        self._torch = torch
+        dg = _as_device_graph(g)
+        self.n = dg.n
+        self.stream = stream
+        self._opts = _opts("degree", False, stream, None, waves_per_cu, donate_interval, 0)
+        h = ctypes.c_void_p()
+        res = _Result()
+        csr = dg.csr()
+        _check(lib().imce_create(ctypes.byref(csr), ctypes.byref(self._opts), ctypes.byref(h), ctypes.byref(res)))
+        self._h = h
+        self.initial = {"count": res.count, "set_hash": res.set_hash, "nodes_total": res.nodes_total,
+                        "enum_ms": res.enum_ms}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().imce_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, nnz, c, h = (ctypes.c_uint64() for _ in range(4))
+        _check(lib().imce_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(c), ctypes.byref(h)))
+        return {"n": n.value, "nnz": nnz.value, "count": c.value, "set_hash": h.value}
+
+    def add(self, src, dst, cliques: bool = False, cap_cliques: int = 1 << 14, cap_verts: int = 1 << 18):
+        torch = self._torch
+        s = torch.as_tensor(np.ascontiguousarray(np.asarray(src, dtype=np.uint32)).view(np.int32)).cuda()
+        d = torch.as_tensor(np.ascontiguousarray(np.asarray(dst, dtype=np.uint32)).view(np.int32)).cuda()
+        rho = int(s.numel())
+        res = _ImceResult()
+        if not cliques:
+            _check(lib().imce_add_edges(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
+                                        ctypes.byref(res), None, None))
+            out = {k: getattr(res, k) for k, _ in _ImceResult._fields_}
+            return out
+        cc, cv = cap_cliques, cap_verts
+        for _ in range(3):
+            bufs = []
+            cbs = []
+            for _k in range(2):
+                off = torch.zeros(cc + 1, dtype=torch.int64, device="cuda")
+                vert = torch.zeros(max(cv, 1), dtype=torch.int32, device="cuda")
+                bufs.append((off, vert))
+                cbs.append(_CliqueBuf(cc, cv, off.data_ptr(), vert.data_ptr(), 1, 0, 0))
+            rc = lib().imce_add_edges(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
+                                      ctypes.byref(res), ctypes.byref(cbs[0]), ctypes.byref(cbs[1]))
+            if rc == MCE_ENOSPC:
+                cc = max(cc, int(cbs[0].n_cliques), int(cbs[1].n_cliques))
+                cv = max(cv, int(cbs[0].n_verts), int(cbs[1].n_verts))
+                continue
+            _check(rc)
+            out = {k: getattr(res, k) for k, _ in _ImceResult._fields_}
+            for name, cb, (off, vert) in zip(("new", "del"), cbs, bufs):
+                nc = int(cb.n_cliques)
+                offn = off[:nc + 1].cpu().numpy().view(np.uint64)
+                vn = vert[:int(cb.n_verts)].cpu().numpy().view(np.uint32)
+                out[name] = sorted(_decode_cliques(offn, vn, nc))
+            return out
+        raise MceError(MCE_ENOSPC, "clique buffer sizing did not converge")

@@ -1,20 +1,924 @@
-// Incremental maintenance (Section 5): placeholder entry points.
+// Incremental maintenance of the maximal cliques under edge additions
+// (Section 5).  One batch H:
+//   1. canonicalise: reject self-loops / ids >= n; normalise (min, max); drop
+//      pairs already in G and repeats (first occurrence wins); survivors in
+//      input order are e_1..e_rho (Algorithm 5 takes them in any fixed order);
+//   2. G' = G + H into a second CSR buffer (G stays intact until commit);
+//   3. new cliques (Algorithms 5, 6, 8): one edge subproblem per e_i = (u, v)
+//      with K = {u, v}, cand = Gamma'(u) n Gamma'(v), fini = {}; a child q is
+//      skipped (and moved to fini) when K u {q} contains e_j, j < i.  The
+//      persistent search kernel runs these subproblems in exclusion mode and
+//      writes the new cliques to a device buffer;
+//   4. subsumed cliques (Algorithm 7): each new clique c is split along its
+//      batch edges into edge-free subsets; such a subset c' is a clique of G,
+//      and c' is in C(G) iff no vertex outside c' is adjacent in G to all of
+//      it (the stored-set test of Algorithm 7 in its equivalent form, checked
+//      against the stored set by the oracle).  Candidates are de-duplicated
+//      exactly, so each subsumed clique is reported once;
+//   5. commit: G <- G', count += |new| - |del|, hash += H(new) - H(del).
+// Any error before step 5 leaves the state unchanged.
+
+#include <hipcub/hipcub.hpp>
+
+#include <cstring>
+#include <vector>
+
+#include "dev.h"
 #include "internal.h"
 
 using namespace mce;
 
-struct imce_state { int unused; };
+struct imce_state {
+  uint64_t n = 0, nnz = 0;
+  DevBuf rp[2], col[2];
+  int cur = 0;
+  uint64_t count = 0, hash = 0;
+  mce_opts opts;
+  DevBuf bsrc, bdst, keys, idx, keys2, idx2, keep, pos, eu, ev, hkeys, hidx, hkeys2, hidx2, dkeys, didx, dkeys2, didx2,
+      addcnt, degw, p, x, words, gwords, off, goff, stats, arena, gids, order, bad, new_off, new_vert, cand_off,
+      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, del_off, del_vert;
+  uint64_t cap_nc = 0, cap_nv = 0, cap_cc = 0, cap_cv = 0;
+  EnumWork ew;
+  void* scan_tmp = nullptr;
+  size_t scan_bytes = 0;
+  void* sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+};
+
+namespace {
+
+inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
+
+constexpr uint32_t kSubMaxK = 64;     // largest new clique the subsumed kernel takes
+constexpr uint32_t kSubMaxS = 1024;   // candidate subsets per new clique
+constexpr uint32_t kSubMaxPairs = 256;
+
+// -- 1. canonicalisation -------------------------------------------------------
+
+__global__ void k_canon(uint64_t rho, const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t n,
+                        uint64_t* keys, uint32_t* idx, uint32_t* bad) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= rho) return;
+  uint32_t a = src[i], b = dst[i];
+  if (a >= n || b >= n || a == b) {
+    atomicOr(bad, 1u);
+    keys[i] = 0;
+  } else {
+    uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    keys[i] = lo * n + hi;
+  }
+  idx[i] = (uint32_t)i;
+}
+
+// After a stable sort by key: the first occurrence of each key survives
+// unless the edge is already in G.
+__global__ void k_keep(uint64_t rho, const uint64_t* __restrict__ skeys, const uint32_t* __restrict__ sidx, uint64_t n,
+                       const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col, uint64_t* keep) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= rho) return;
+  const uint64_t key = skeys[i];
+  bool first = i == 0 || skeys[i - 1] != key;
+  const uint32_t a = (uint32_t)(key / n), b = (uint32_t)(key % n);
+  bool exists = bsearch_u32(col + rp[a], rp[a + 1] - rp[a], b) >= 0;
+  keep[sidx[i]] = (first && !exists) ? 1 : 0;
+}
+
+__global__ void k_scatter(uint64_t rho, const uint64_t* __restrict__ keep, const uint64_t* __restrict__ pos,
+                          const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t n, uint32_t* eu,
+                          uint32_t* ev, uint64_t* hkeys, uint32_t* hidx, uint64_t* dkeys, uint32_t* didx) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= rho || !keep[i]) return;
+  const uint64_t j = pos[i];
+  const uint32_t a = src[i], b = dst[i];
+  const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  eu[j] = lo;
+  ev[j] = hi;
+  hkeys[j] = (uint64_t)lo * n + hi;
+  hidx[j] = (uint32_t)j;
+  dkeys[2 * j] = (uint64_t)lo * n + hi;
+  didx[2 * j] = (uint32_t)j;
+  dkeys[2 * j + 1] = (uint64_t)hi * n + lo;
+  didx[2 * j + 1] = (uint32_t)j;
+}
+
+// -- 2. G' = G + H ------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t lower_bound_u32(const uint32_t* a, uint64_t n, uint32_t x) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_newdeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ dkeys, uint64_t nd,
+                         uint64_t* degw) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  degw[v] = rp[v + 1] - rp[v] + (hi - lo);
+}
+
+__global__ void k_rp_tail(uint64_t n, uint64_t* rpn, const uint64_t* degw) { rpn[n] = rpn[n - 1] + degw[n - 1]; }
+
+// One wave per vertex: merge the old row with the vertex's new neighbours.
+__global__ void __launch_bounds__(256) k_merge_rows(uint64_t n, const uint64_t* __restrict__ rp,
+                                                    const uint32_t* __restrict__ col, const uint64_t* __restrict__ dkeys,
+                                                    uint64_t nd, const uint64_t* __restrict__ rpn, uint32_t* coln) {
+  const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (v >= n) return;
+  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint64_t t = hi - lo;
+  const uint32_t* row = col + rp[v];
+  const uint64_t d = rp[v + 1] - rp[v];
+  uint32_t* out = coln + rpn[v];
+  for (uint64_t j = lane; j < d; j += kWave) {
+    const uint32_t w = row[j];
+    // new neighbours smaller than w
+    uint64_t a = 0, b = t;
+    while (a < b) {
+      uint64_t mid = (a + b) >> 1;
+      if ((uint32_t)(dkeys[lo + mid] % n) < w) a = mid + 1;
+      else b = mid;
+    }
+    out[j + a] = w;
+  }
+  for (uint64_t k = lane; k < t; k += kWave) {
+    const uint32_t w = (uint32_t)(dkeys[lo + k] % n);
+    out[k + lower_bound_u32(row, d, w)] = w;
+  }
+}
+
+// -- 3. edge subproblems ------------------------------------------------------
+
+// |Gamma'(u) n Gamma'(v)| for every batch edge (one wave per edge).
+__global__ void __launch_bounds__(256) k_edge_sizes(uint64_t m, const uint32_t* __restrict__ eu,
+                                                    const uint32_t* __restrict__ ev, const uint64_t* __restrict__ rp,
+                                                    const uint32_t* __restrict__ col, uint32_t* P, uint32_t* X,
+                                                    uint64_t* words, uint64_t* gwords, uint64_t* stats) {
+  const uint64_t e = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (e >= m) return;
+  uint32_t a = eu[e], b = ev[e];
+  uint64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+  if (da > db) {
+    uint32_t t = a; a = b; b = t;
+    uint64_t tt = da; da = db; db = tt;
+  }
+  uint32_t c = 0;
+  for (uint64_t j = lane; j < da; j += kWave) c += bsearch_u32(col + rp[b], db, col[rp[a] + j]) >= 0 ? 1u : 0u;
+  c = (uint32_t)wave_sum_u64(c);
+  if (lane == 0) {
+    const uint64_t wp = (c + 63) / 64;
+    P[e] = c;
+    X[e] = 0;
+    words[e] = wp * (2ULL * c + 1);
+    gwords[e] = c;
+    atomicMax((unsigned long long*)&stats[0], (unsigned long long)c);
+    atomicMax((unsigned long long*)&stats[1], (unsigned long long)(4 * wp + 1));
+  }
+}
+
+// Vertex-id table of each edge subproblem: the common neighbours, ascending.
+__global__ void __launch_bounds__(256) k_edge_gids(uint64_t m, const uint32_t* __restrict__ eu,
+                                                   const uint32_t* __restrict__ ev, const uint64_t* __restrict__ rp,
+                                                   const uint32_t* __restrict__ col, const uint64_t* __restrict__ goff,
+                                                   uint32_t* gids) {
+  const uint64_t e = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (e >= m) return;
+  uint32_t a = eu[e], b = ev[e];
+  uint64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+  if (da > db) {
+    uint32_t t = a; a = b; b = t;
+    uint64_t tt = da; da = db; db = tt;
+  }
+  uint32_t* g = gids + goff[e];
+  uint32_t cnt = 0;
+  for (uint64_t c0 = 0; c0 < da; c0 += kWave) {
+    const uint64_t j = c0 + lane;
+    const uint32_t w = j < da ? col[rp[a] + j] : 0;
+    const bool in = j < da && bsearch_u32(col + rp[b], db, w) >= 0;
+    const uint64_t bm = ballot(in);
+    if (in) g[cnt + mask_prefix(bm, lane)] = w;
+    cnt += (uint32_t)__popcll(bm);
+  }
+}
+
+// Bit rows of each edge subproblem: adjacency among the common neighbours
+// (word-major), exclusion rows excl[a] = {b : (g[a], g[b]) = e_j, j < i} and
+// the root exclusion set F0 = {a : (g[a], u) or (g[a], v) = e_j, j < i}.
+__global__ void __launch_bounds__(256) k_edge_rows(uint64_t m, const uint32_t* __restrict__ eu,
+                                                   const uint32_t* __restrict__ ev, const uint64_t* __restrict__ rp,
+                                                   const uint32_t* __restrict__ col, const uint32_t* __restrict__ P,
+                                                   const uint64_t* __restrict__ off, const uint64_t* __restrict__ goff,
+                                                   const uint32_t* __restrict__ gids, const uint64_t* __restrict__ dkeys,
+                                                   const uint32_t* __restrict__ didx, uint64_t nd, uint64_t n,
+                                                   uint64_t* arena) {
+  const uint64_t e = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (e >= m) return;
+  const uint32_t p = P[e];
+  if (p == 0) return;
+  const uint64_t wp = (p + 63) / 64;
+  uint64_t* rowP = arena + off[e];
+  uint64_t* excl = rowP + wp * p;
+  uint64_t* F0 = excl + (uint64_t)p * wp;
+  const uint32_t* g = gids + goff[e];
+  const uint32_t u = eu[e], v = ev[e];
+  for (uint32_t a = 0; a < p; ++a) {
+    const uint32_t q = g[a];
+    for (uint64_t j = rp[q] + lane; j < rp[q + 1]; j += kWave) {
+      const int64_t b = bsearch_u32(g, p, col[j]);
+      if (b >= 0) atomicOr((unsigned long long*)&rowP[(uint64_t)(b >> 6) * p + a], 1ULL << (b & 63));
+    }
+    const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)q * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(q + 1) * n);
+    for (uint64_t k = lo + lane; k < hi; k += kWave) {
+      if (didx[k] >= e) continue;  // only e_j with j < i are excluded
+      const uint32_t w = (uint32_t)(dkeys[k] % n);
+      if (w == u || w == v) {
+        atomicOr((unsigned long long*)&F0[a >> 6], 1ULL << (a & 63));
+      } else {
+        const int64_t b = bsearch_u32(g, p, w);
+        if (b >= 0) atomicOr((unsigned long long*)&excl[(uint64_t)a * wp + (b >> 6)], 1ULL << (b & 63));
+      }
+    }
+  }
+}
+
+__global__ void k_iota32(uint64_t n, uint32_t* a) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (uint32_t)i;
+}
+
+// -- 4. subsumed cliques --------------------------------------------------------
+
+struct SubLds {
+  uint32_t c[kSubMaxK];
+  uint64_t pairs[kSubMaxPairs];
+  uint64_t S[2][kSubMaxS];
+  uint32_t np, ns;
+};
+
+// sctl: [0] packed candidate counter (cands << 32 | verts), [1] flags
+// (1: clique too large, 2: too many subsets or pairs, 4: candidate overflow)
+__global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint64_t* __restrict__ noff,
+                                                 const uint32_t* __restrict__ nvert, uint64_t n,
+                                                 const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                                                 const uint64_t* __restrict__ hkeys, uint64_t nh,
+                                                 const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* sctl,
+                                                 uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
+                                                 uint64_t cap_c, uint64_t cap_v) {
+  __shared__ SubLds L;
+  const int lane = threadIdx.x;
+  for (uint64_t ci = blockIdx.x; ci < nnew; ci += gridDim.x) {
+    const uint64_t b0 = noff[ci];
+    const uint32_t k = (uint32_t)(noff[ci + 1] - b0);
+    if (k > kSubMaxK) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 1ULL);
+      continue;
+    }
+    if (lane < (int)k) L.c[lane] = nvert[b0 + lane];
+    if (lane == 0) L.np = 0;
+    __syncthreads();
+    // batch edges inside c: lane j walks the new neighbours of c[j]
+    if (lane < (int)k) {
+      const uint32_t x = L.c[lane];
+      const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)x * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(x + 1) * n);
+      for (uint64_t t = lo; t < hi; ++t) {
+        const uint32_t w = (uint32_t)(dkeys[t] % n);
+        if (w <= x) continue;  // each pair once
+        const int64_t j2 = bsearch_u32(L.c, k, w);
+        if (j2 >= 0) {
+          uint32_t slot = atomicAdd(&L.np, 1u);
+          if (slot < kSubMaxPairs) L.pairs[slot] = (1ULL << lane) | (1ULL << j2);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t npairs = L.np;
+    if (npairs > kSubMaxPairs) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      __syncthreads();
+      continue;
+    }
+    // Algorithm 7: split every subset that holds both ends of a batch edge
+    int cur = 0;
+    uint32_t ns = 1;
+    if (lane == 0) L.S[0][0] = k == 64 ? ~0ULL : ((1ULL << k) - 1);
+    bool overflow = false;
+    for (uint32_t e = 0; e < npairs && !overflow; ++e) {
+      __syncthreads();
+      const uint64_t pm = L.pairs[e];
+      const uint64_t bx = pm & (~pm + 1), by = pm & ~bx;
+      uint32_t nout = 0;
+      for (uint32_t base = 0; base < ns; base += kWave) {
+        const uint32_t i = base + lane;
+        const uint64_t sm = i < ns ? L.S[cur][i] : 0;
+        const bool split = i < ns && (sm & pm) == pm;
+        const bool keep1 = i < ns && !split;
+        const uint32_t cnt = split ? 2u : (keep1 ? 1u : 0u);
+        const uint32_t incl = wave_incl_scan_u32(cnt);
+        const uint32_t total = readlane32(incl, 63);
+        if (nout + total > kSubMaxS) {
+          overflow = true;
+          break;
+        }
+        const uint32_t o = nout + incl - cnt;
+        if (split) {
+          L.S[cur ^ 1][o] = sm & ~bx;
+          L.S[cur ^ 1][o + 1] = sm & ~by;
+        } else if (keep1) {
+          L.S[cur ^ 1][o] = sm;
+        }
+        nout += total;
+      }
+      cur ^= 1;
+      ns = nout;
+    }
+    __syncthreads();
+    if (overflow) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      continue;
+    }
+    // each distinct subset once (first occurrence), then the maximality test in G
+    for (uint32_t i = 0; i < ns; ++i) {
+      const uint64_t sm = L.S[cur][i];
+      bool dup = false;
+      for (uint32_t j = lane; j < i && !dup; j += kWave) dup = L.S[cur][j] == sm;
+      if (ballot(dup)) continue;
+      // the member of c' with the smallest degree in G
+      const bool mem = lane < (int)k && ((sm >> lane) & 1ULL);
+      const uint32_t x = mem ? L.c[lane] : 0;
+      const uint64_t dx = mem ? rp[x + 1] - rp[x] : ~0ULL;
+      const uint64_t key = mem ? ((dx << 7) | (uint64_t)lane) : ~0ULL;
+      uint64_t mn = key;
+      for (int o = 32; o >= 1; o >>= 1) {
+        uint64_t t = __shfl_xor(mn, o, kWave);
+        mn = t < mn ? t : mn;
+      }
+      const int la = (int)(mn & 127);
+      const uint32_t a = L.c[la];
+      // is some w outside c' adjacent in G to every vertex of c'?
+      bool extends = false;
+      const uint64_t ab = rp[a], ae = rp[a + 1];
+      for (uint64_t j0 = ab; j0 < ae; j0 += kWave) {
+        const uint64_t j = j0 + lane;
+        bool ok = j < ae;
+        uint32_t w = ok ? col[j] : 0;
+        if (ok) {
+          const int64_t pos = bsearch_u32(L.c, k, w);
+          if (pos >= 0 && ((sm >> pos) & 1ULL)) ok = false;
+        }
+        uint64_t rest = sm & ~(1ULL << la);
+        while (ok && rest) {
+          const int y = __builtin_ctzll(rest);
+          rest &= rest - 1;
+          const uint32_t yy = L.c[y];
+          ok = bsearch_u32(col + rp[yy], rp[yy + 1] - rp[yy], w) >= 0;
+        }
+        if (ballot(ok)) {
+          extends = true;
+          break;
+        }
+      }
+      if (extends) continue;
+      // c' is a maximal clique of G: a subsumed-clique candidate
+      const uint32_t kk = (uint32_t)__popcll(sm);
+      uint64_t old = 0;
+      if (lane == 0) old = atomicAdd((unsigned long long*)&sctl[0], (unsigned long long)((1ULL << 32) | kk));
+      old = readlane64(old, 0);
+      const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+      if (id >= cap_c || pos + kk > cap_v) {
+        if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 4ULL);
+        continue;
+      }
+      const uint64_t below = mem ? __popcll(sm & ((1ULL << lane) - 1)) : 0;
+      if (mem) cand_vert[pos + below] = x;
+      const uint64_t z = wave_sum_u64(mem ? mix64(x) : 0);
+      if (lane == 0) {
+        cand_off[id] = pos;
+        cand_hash[id] = clique_term(z, kk);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// After sorting candidates by hash: a candidate is kept unless an earlier one
+// of the same hash run has the same vertex list.  Kept ones are counted,
+// hashed and (optionally) written out.
+__global__ void k_dedup(uint64_t nc, const uint64_t* __restrict__ shash, const uint32_t* __restrict__ sid,
+                        const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand_vert,
+                        uint64_t total_verts, uint64_t* uniq_ctl,
+                        uint64_t* out_off, uint32_t* out_vert, uint64_t cap_c, uint64_t cap_v) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  const uint32_t me = sid[i];
+  const uint64_t b = cand_off[me];
+  const uint64_t e = (uint64_t)me + 1 < nc ? cand_off[me + 1] : total_verts;
+  const uint64_t len = e - b;
+  bool dup = false;
+  for (uint64_t j = i; j > 0 && !dup;) {
+    --j;
+    if (shash[j] != shash[i]) break;
+    const uint32_t o = sid[j];
+    const uint64_t ob = cand_off[o];
+    const uint64_t oe = (uint64_t)o + 1 < nc ? cand_off[o + 1] : total_verts;
+    if (oe - ob != len) continue;
+    bool same = true;
+    for (uint64_t t = 0; t < len && same; ++t) same = cand_vert[ob + t] == cand_vert[b + t];
+    dup = same;
+  }
+  if (dup) return;
+  atomicAdd((unsigned long long*)&uniq_ctl[0], 1ULL);
+  atomicAdd((unsigned long long*)&uniq_ctl[1], (unsigned long long)shash[i]);
+  if (out_vert) {
+    uint64_t old = atomicAdd((unsigned long long*)&uniq_ctl[2], (unsigned long long)((1ULL << 32) | len));
+    uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+    if (id < cap_c && pos + len <= cap_v) {
+      out_off[id] = pos;
+      for (uint64_t t = 0; t < len; ++t) out_vert[pos + t] = cand_vert[b + t];
+    }
+  }
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
+
+int sort_pairs_u64_u32(imce_state* st, uint64_t* k, uint32_t* v, uint64_t* k2, uint32_t* v2, uint64_t nitems,
+                       hipStream_t s, uint64_t** ko, uint32_t** vo) {
+  hipcub::DoubleBuffer<uint64_t> kb(k, k2);
+  hipcub::DoubleBuffer<uint32_t> vb(v, v2);
+  size_t need = 0;
+  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)nitems, 0, 64, s));
+  if (need > st->sort_bytes) {
+    if (st->sort_tmp) MCE_TRY_HIP(hipFree(st->sort_tmp));
+    st->sort_tmp = nullptr;
+    st->sort_bytes = 0;
+    MCE_TRY_HIP(hipMalloc(&st->sort_tmp, need));
+    st->sort_bytes = need;
+  }
+  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(st->sort_tmp, need, kb, vb, (int)nitems, 0, 64, s));
+  *ko = kb.Current();
+  *vo = vb.Current();
+  return MCE_OK;
+}
+
+int copy_cliques_out(mce_clique_buf* out, const uint64_t* off, const uint32_t* vert, uint64_t nc, uint64_t nv,
+                     hipStream_t s) {
+  out->n_cliques = nc;
+  out->n_verts = nv;
+  if (nc > out->cap_cliques || nv > out->cap_verts || (nc && !out->off) || (nv && !out->vert)) return MCE_ENOSPC;
+  const hipMemcpyKind kind = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (out->off) {
+    if (nc) MCE_TRY_HIP(hipMemcpyAsync(out->off, off, nc * sizeof(uint64_t), kind, s));
+    if (out->on_device) {
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, out->off + nc, nv);
+      MCE_TRY_HIP(hipGetLastError());
+    } else {
+      MCE_TRY_HIP(hipStreamSynchronize(s));
+      out->off[nc] = nv;
+    }
+  }
+  if (nv) MCE_TRY_HIP(hipMemcpyAsync(out->vert, vert, nv * sizeof(uint32_t), kind, s));
+  return MCE_OK;
+}
+
+int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                   imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+  hipStream_t s = (hipStream_t)st->opts.hip_stream;
+  std::memset(res, 0, sizeof(*res));
+  const uint64_t n = st->n;
+  res->count = st->count;
+  res->set_hash = st->hash;
+  if (new_cl) new_cl->n_cliques = new_cl->n_verts = 0;
+  if (del_cl) del_cl->n_cliques = del_cl->n_verts = 0;
+  if (rho == 0) return MCE_OK;
+  if (!src || !dst) {
+    set_error("NULL batch arrays");
+    return MCE_EINVAL;
+  }
+  hipEvent_t ev[4];
+  for (auto& e : ev) MCE_TRY_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  MCE_TRY_HIP(hipEventRecord(ev[0], s));
+
+  const uint64_t* rp = st->rp[st->cur].as<uint64_t>();
+  const uint32_t* col = st->col[st->cur].as<uint32_t>();
+  const uint32_t* dsrc = src;
+  const uint32_t* ddst = dst;
+  if (!on_device) {
+    MCE_TRY(st->bsrc.ensure(rho * sizeof(uint32_t)));
+    MCE_TRY(st->bdst.ensure(rho * sizeof(uint32_t)));
+    MCE_TRY_HIP(hipMemcpyAsync(st->bsrc.p, src, rho * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    MCE_TRY_HIP(hipMemcpyAsync(st->bdst.p, dst, rho * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    dsrc = st->bsrc.as<uint32_t>();
+    ddst = st->bdst.as<uint32_t>();
+  }
+
+  // 1. canonicalise
+  MCE_TRY(st->keys.ensure(rho * 8));
+  MCE_TRY(st->keys2.ensure(rho * 8));
+  MCE_TRY(st->idx.ensure(rho * 4));
+  MCE_TRY(st->idx2.ensure(rho * 4));
+  MCE_TRY(st->keep.ensure(rho * 8));
+  MCE_TRY(st->pos.ensure(rho * 8));
+  MCE_TRY(st->bad.ensure(8));
+  MCE_TRY_HIP(hipMemsetAsync(st->bad.p, 0, 4, s));
+  hipLaunchKernelGGL(k_canon, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, dsrc, ddst, n, st->keys.as<uint64_t>(),
+                     st->idx.as<uint32_t>(), st->bad.as<uint32_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  uint32_t bad = 0;
+  MCE_TRY_HIP(hipMemcpyAsync(&bad, st->bad.p, 4, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  if (bad) {
+    set_error("batch has a self-loop or a vertex id >= n");
+    return MCE_EINVAL;
+  }
+  uint64_t* skeys;
+  uint32_t* sidx;
+  MCE_TRY(sort_pairs_u64_u32(st, st->keys.as<uint64_t>(), st->idx.as<uint32_t>(), st->keys2.as<uint64_t>(),
+                             st->idx2.as<uint32_t>(), rho, s, &skeys, &sidx));
+  hipLaunchKernelGGL(k_keep, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, skeys, sidx, n, rp, col,
+                     st->keep.as<uint64_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  MCE_TRY(device_exclusive_scan(st->keep.as<uint64_t>(), st->pos.as<uint64_t>(), rho, st->scan_tmp, st->scan_bytes, s));
+  uint64_t lastpos = 0, lastkeep = 0;
+  MCE_TRY_HIP(hipMemcpyAsync(&lastpos, st->pos.as<uint64_t>() + rho - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&lastkeep, st->keep.as<uint64_t>() + rho - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  const uint64_t m = lastpos + lastkeep;  // applied edges
+  res->n_applied = m;
+  res->n_skipped = rho - m;
+  if (m == 0) {
+    MCE_TRY_HIP(hipEventRecord(ev[3], s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    float t = 0;
+    (void)hipEventElapsedTime(&t, ev[0], ev[3]);
+    res->ms = t;
+    return MCE_OK;
+  }
+  const uint64_t nd = 2 * m;
+  MCE_TRY(st->eu.ensure(m * 4));
+  MCE_TRY(st->ev.ensure(m * 4));
+  MCE_TRY(st->hkeys.ensure(m * 8));
+  MCE_TRY(st->hidx.ensure(m * 4));
+  MCE_TRY(st->hkeys2.ensure(m * 8));
+  MCE_TRY(st->hidx2.ensure(m * 4));
+  MCE_TRY(st->dkeys.ensure(nd * 8));
+  MCE_TRY(st->didx.ensure(nd * 4));
+  MCE_TRY(st->dkeys2.ensure(nd * 8));
+  MCE_TRY(st->didx2.ensure(nd * 4));
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, st->keep.as<uint64_t>(),
+                     st->pos.as<uint64_t>(), dsrc, ddst, n, st->eu.as<uint32_t>(), st->ev.as<uint32_t>(),
+                     st->hkeys.as<uint64_t>(), st->hidx.as<uint32_t>(), st->dkeys.as<uint64_t>(), st->didx.as<uint32_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  uint64_t* hk;
+  uint32_t* hi;
+  MCE_TRY(sort_pairs_u64_u32(st, st->hkeys.as<uint64_t>(), st->hidx.as<uint32_t>(), st->hkeys2.as<uint64_t>(),
+                             st->hidx2.as<uint32_t>(), m, s, &hk, &hi));
+  uint64_t* dk;
+  uint32_t* di;
+  MCE_TRY(sort_pairs_u64_u32(st, st->dkeys.as<uint64_t>(), st->didx.as<uint32_t>(), st->dkeys2.as<uint64_t>(),
+                             st->didx2.as<uint32_t>(), nd, s, &dk, &di));
+
+  // 2. G' = G + H
+  const int nxt = st->cur ^ 1;
+  const uint64_t nnz2 = st->nnz + nd;
+  MCE_TRY(st->degw.ensure(n * 8));
+  MCE_TRY(st->rp[nxt].ensure((n + 1) * 8));
+  MCE_TRY(st->col[nxt].ensure(std::max<uint64_t>(nnz2, 1) * 4));
+  uint64_t* rpn = st->rp[nxt].as<uint64_t>();
+  uint32_t* coln = st->col[nxt].as<uint32_t>();
+  hipLaunchKernelGGL(k_newdeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  MCE_TRY(device_exclusive_scan(st->degw.as<uint64_t>(), rpn, n, st->scan_tmp, st->scan_bytes, s));
+  hipLaunchKernelGGL(k_rp_tail, dim3(1), dim3(1), 0, s, n, rpn, st->degw.as<uint64_t>());
+  hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
+  MCE_TRY_HIP(hipGetLastError());
+
+  // 3. new cliques: one edge subproblem per applied edge
+  MCE_TRY(st->p.ensure(m * 4));
+  MCE_TRY(st->x.ensure(m * 4));
+  MCE_TRY(st->words.ensure(m * 8));
+  MCE_TRY(st->gwords.ensure(m * 8));
+  MCE_TRY(st->off.ensure(m * 8));
+  MCE_TRY(st->goff.ensure(m * 8));
+  MCE_TRY(st->order.ensure(m * 4));
+  MCE_TRY(st->stats.ensure(8 * 8));
+  MCE_TRY_HIP(hipMemsetAsync(st->stats.p, 0, 64, s));
+  hipLaunchKernelGGL(k_edge_sizes, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
+                     st->ev.as<uint32_t>(), rpn, coln, st->p.as<uint32_t>(), st->x.as<uint32_t>(),
+                     st->words.as<uint64_t>(), st->gwords.as<uint64_t>(), st->stats.as<uint64_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  MCE_TRY(device_exclusive_scan(st->words.as<uint64_t>(), st->off.as<uint64_t>(), m, st->scan_tmp, st->scan_bytes, s));
+  MCE_TRY(device_exclusive_scan(st->gwords.as<uint64_t>(), st->goff.as<uint64_t>(), m, st->scan_tmp, st->scan_bytes, s));
+  uint64_t stats[8], tl[4];
+  MCE_TRY_HIP(hipMemcpyAsync(stats, st->stats.p, 64, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tl[0], st->off.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tl[1], st->words.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tl[2], st->goff.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipMemcpyAsync(&tl[3], st->gwords.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  if (stats[0] > kMaxCand) {
+    set_error("an edge subproblem has %llu common neighbours; at most %u are supported",
+              (unsigned long long)stats[0], kMaxCand);
+    return MCE_ENOTSUP;
+  }
+  const uint64_t aw = std::max<uint64_t>(tl[0] + tl[1], 1), gw = std::max<uint64_t>(tl[2] + tl[3], 1);
+  MCE_TRY(st->arena.ensure(aw * 8));
+  MCE_TRY(st->gids.ensure(gw * 4));
+  MCE_TRY_HIP(hipMemsetAsync(st->arena.p, 0, aw * 8, s));
+  hipLaunchKernelGGL(k_edge_gids, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
+                     st->ev.as<uint32_t>(), rpn, coln, st->goff.as<uint64_t>(), st->gids.as<uint32_t>());
+  hipLaunchKernelGGL(k_edge_rows, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
+                     st->ev.as<uint32_t>(), rpn, coln, st->p.as<uint32_t>(), st->off.as<uint64_t>(),
+                     st->goff.as<uint64_t>(), st->gids.as<uint32_t>(), dk, di, nd, n, st->arena.as<uint64_t>());
+  hipLaunchKernelGGL(k_iota32, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, st->order.as<uint32_t>());
+  MCE_TRY_HIP(hipGetLastError());
+
+  if (st->cap_nc == 0) {
+    st->cap_nc = 1 << 20;
+    st->cap_nv = 1 << 24;
+  }
+  uint64_t ctl[CTL_WORDS];
+  for (int attempt = 0;; ++attempt) {
+    MCE_TRY(st->new_off.ensure((st->cap_nc + 1) * 8));
+    MCE_TRY(st->new_vert.ensure(st->cap_nv * 4));
+    EnumJob job;
+    job.sub.off = st->off.as<uint64_t>();
+    job.sub.goff = st->goff.as<uint64_t>();
+    job.sub.p = st->p.as<uint32_t>();
+    job.sub.x = st->x.as<uint32_t>();
+    job.sub.r0 = st->eu.as<uint32_t>();
+    job.sub.r1 = st->ev.as<uint32_t>();
+    job.arena = st->arena.as<uint64_t>();
+    job.gids = st->gids.as<uint32_t>();
+    job.nq = m;
+    job.order = st->order.as<uint32_t>();
+    job.max_p = stats[0];
+    job.max_frame = stats[1];
+    job.excl = true;
+    job.nodes_v = job.count_v = job.hash_v = nullptr;
+    job.cl_off = st->new_off.as<uint64_t>();
+    job.cl_vert = st->new_vert.as<uint32_t>();
+    job.cap_cliques = st->cap_nc;
+    job.cap_verts = st->cap_nv;
+    job.opts = &st->opts;
+    MCE_TRY(run_enum(job, st->ew, s, ctl, nullptr));
+    if (ctl[CTL_FLAGS] & 2ULL) {
+      set_error("new cliques exceed 2^32 vertices or a clique exceeds the supported size");
+      return MCE_ENOTSUP;
+    }
+    const uint64_t nc = ctl[CTL_CLQ] >> 32, nv = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
+    if (nc <= st->cap_nc && nv <= st->cap_nv) break;
+    if (attempt >= 2) {
+      set_error("new-clique buffer sizing did not converge");
+      return MCE_ENOMEM;
+    }
+    st->cap_nc = std::max(st->cap_nc, nc);
+    st->cap_nv = std::max(st->cap_nv, nv);
+  }
+  const uint64_t n_new = ctl[CTL_COUNT], h_new = ctl[CTL_HASH];
+  const uint64_t nc_new = ctl[CTL_CLQ] >> 32, nv_new = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
+  MCE_TRY_HIP(hipEventRecord(ev[1], s));
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, st->new_off.as<uint64_t>() + nc_new, nv_new);
+
+  // 4. subsumed cliques
+  if (st->cap_cc == 0) {
+    st->cap_cc = 1 << 20;
+    st->cap_cv = 1 << 24;
+  }
+  uint64_t sctl[2];
+  for (int attempt = 0;; ++attempt) {
+    MCE_TRY(st->cand_off.ensure((st->cap_cc + 1) * 8));
+    MCE_TRY(st->cand_vert.ensure(st->cap_cv * 4));
+    MCE_TRY(st->cand_hash.ensure(st->cap_cc * 8));
+    MCE_TRY(st->sctl.ensure(4 * 8));
+    MCE_TRY_HIP(hipMemsetAsync(st->sctl.p, 0, 32, s));
+    if (nc_new) {
+      const uint32_t grid = (uint32_t)std::min<uint64_t>(nc_new, 8192);
+      hipLaunchKernelGGL(k_subsumed, dim3(grid), dim3(64), 0, s, nc_new, st->new_off.as<uint64_t>(),
+                         st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd, st->sctl.as<uint64_t>(),
+                         st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(),
+                         st->cap_cc, st->cap_cv);
+      MCE_TRY_HIP(hipGetLastError());
+    }
+    MCE_TRY_HIP(hipMemcpyAsync(sctl, st->sctl.p, 16, hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    if (sctl[1] & 3ULL) {
+      set_error("a new clique exceeds %u vertices or splits into more than %u subsets", kSubMaxK, kSubMaxS);
+      return MCE_ENOTSUP;
+    }
+    if (!(sctl[1] & 4ULL)) break;
+    if (attempt >= 2) {
+      set_error("candidate buffer sizing did not converge");
+      return MCE_ENOMEM;
+    }
+    st->cap_cc = std::max<uint64_t>(st->cap_cc, sctl[0] >> 32);
+    st->cap_cv = std::max<uint64_t>(st->cap_cv, sctl[0] & 0xFFFFFFFFULL);
+  }
+  const uint64_t ncand = sctl[0] >> 32, nvcand = sctl[0] & 0xFFFFFFFFULL;
+  uint64_t uctl[3] = {0, 0, 0};
+  MCE_TRY(st->uniq.ensure(4 * 8));
+  MCE_TRY_HIP(hipMemsetAsync(st->uniq.p, 0, 32, s));
+  uint64_t del_cap_c = 0, del_cap_v = 0;
+  if (del_cl) {
+    del_cap_c = nvcand ? ncand : 0;
+    del_cap_v = nvcand;
+    MCE_TRY(st->del_off.ensure((ncand + 1) * 8));
+    MCE_TRY(st->del_vert.ensure(std::max<uint64_t>(nvcand, 1) * 4));
+  }
+  if (ncand) {
+    MCE_TRY(st->cand_id.ensure(ncand * 4));
+    MCE_TRY(st->chash2.ensure(ncand * 8));
+    MCE_TRY(st->cid2.ensure(ncand * 4));
+    hipLaunchKernelGGL(k_iota32, dim3(blocks_for(ncand, 256)), dim3(256), 0, s, ncand, st->cand_id.as<uint32_t>());
+    // sorting reorders the hash array in place: keep the per-candidate hashes
+    MCE_TRY_HIP(hipMemcpyAsync(st->chash2.p, st->cand_hash.p, ncand * 8, hipMemcpyDeviceToDevice, s));
+    uint64_t* sh;
+    uint32_t* sid;
+    MCE_TRY(st->chash3.ensure(ncand * 8));
+    MCE_TRY(sort_pairs_u64_u32(st, st->chash2.as<uint64_t>(), st->cand_id.as<uint32_t>(), st->chash3.as<uint64_t>(),
+                               st->cid2.as<uint32_t>(), ncand, s, &sh, &sid));
+    hipLaunchKernelGGL(k_dedup, dim3(blocks_for(ncand, 256)), dim3(256), 0, s, ncand, sh, sid,
+                       st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), nvcand,
+                       st->uniq.as<uint64_t>(), del_cl ? st->del_off.as<uint64_t>() : nullptr,
+                       del_cl ? st->del_vert.as<uint32_t>() : nullptr, del_cap_c, del_cap_v);
+    MCE_TRY_HIP(hipGetLastError());
+    MCE_TRY_HIP(hipMemcpyAsync(uctl, st->uniq.p, 24, hipMemcpyDeviceToHost, s));
+  }
+  MCE_TRY_HIP(hipEventRecord(ev[2], s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  const uint64_t n_del = uctl[0], h_del = uctl[1];
+
+  // caller buffers: report sizes; too small -> no commit
+  int rc = MCE_OK;
+  if (new_cl) {
+    int r = copy_cliques_out(new_cl, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), nc_new, nv_new, s);
+    if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
+    else if (r != MCE_OK) return r;
+  }
+  if (del_cl) {
+    const uint64_t dnc = uctl[2] >> 32, dnv = uctl[2] & 0xFFFFFFFFULL;
+    int r = copy_cliques_out(del_cl, st->del_off.as<uint64_t>(), st->del_vert.as<uint32_t>(), dnc, dnv, s);
+    if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
+    else if (r != MCE_OK) return r;
+  }
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  if (rc != MCE_OK) {
+    set_error("clique buffer too small (sizes written back); the batch was not applied");
+    return rc;
+  }
+
+  // 5. commit
+  st->cur = nxt;
+  st->nnz = nnz2;
+  st->count = st->count + n_new - n_del;
+  st->hash = st->hash + h_new - h_del;
+  res->n_new = n_new;
+  res->n_del = n_del;
+  res->hash_new = h_new;
+  res->hash_del = h_del;
+  res->count = st->count;
+  res->set_hash = st->hash;
+  MCE_TRY_HIP(hipEventRecord(ev[3], s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  float t01 = 0, t12 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+  (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+  (void)hipEventElapsedTime(&t03, ev[0], ev[3]);
+  res->new_ms = t01;
+  res->sub_ms = t12;
+  res->ms = t03;
+  return MCE_OK;
+}
+
+void release_state(imce_state* st) {
+  DevBuf* bufs[] = {&st->rp[0], &st->rp[1], &st->col[0], &st->col[1], &st->bsrc, &st->bdst, &st->keys, &st->idx,
+                    &st->keys2, &st->idx2, &st->keep, &st->pos, &st->eu, &st->ev, &st->hkeys, &st->hidx,
+                    &st->hkeys2, &st->hidx2, &st->dkeys, &st->didx, &st->dkeys2, &st->didx2, &st->addcnt,
+                    &st->degw, &st->p, &st->x, &st->words, &st->gwords, &st->off, &st->goff, &st->stats,
+                    &st->arena, &st->gids, &st->order, &st->bad, &st->new_off, &st->new_vert, &st->cand_off,
+                    &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq,
+                    &st->sctl,
+                    &st->del_off, &st->del_vert, &st->ew.queue, &st->ew.ctl, &st->ew.pool, &st->ew.pool_next,
+                    &st->ew.stacks};
+  for (DevBuf* b : bufs) b->release();
+  if (st->scan_tmp) (void)hipFree(st->scan_tmp);
+  if (st->sort_tmp) (void)hipFree(st->sort_tmp);
+  st->scan_tmp = st->sort_tmp = nullptr;
+}
+
+}  // namespace
 
 extern "C" {
-int imce_create(const mce_csr*, const mce_opts*, imce_state**, mce_result*) {
-  set_error("imce_create: not built yet");
-  return MCE_ENOTSUP;
+
+int imce_create(const mce_csr* g, const mce_opts* opts, imce_state** out, mce_result* initial) {
+  if (!g || !out) {
+    set_error("NULL graph or output");
+    return MCE_EINVAL;
+  }
+  *out = nullptr;
+  if (g->n >= 0xFFFFFFFFULL) {
+    set_error("n must be below 2^32 - 1");
+    return MCE_ENOTSUP;
+  }
+  imce_state* st = new imce_state();
+  std::memset(&st->opts, 0, sizeof(st->opts));
+  if (opts) st->opts = *opts;
+  st->opts.sched = MCE_SCHED_DEGREE;
+  st->opts.sched_cost = nullptr;
+  hipStream_t s = (hipStream_t)st->opts.hip_stream;
+  const uint64_t n = g->n;
+  st->n = n;
+  auto fail = [&](int rc) {
+    release_state(st);
+    delete st;
+    return rc;
+  };
+  uint64_t nnz = 0;
+  if (n > 0 && !g->row_ptr) {
+    set_error("row_ptr is NULL");
+    return fail(MCE_EINVAL);
+  }
+  if (n > 0) {
+    if (g->on_device) {
+      if (hipMemcpyAsync(&nnz, g->row_ptr + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        set_error("reading row_ptr[n] failed");
+        return fail(MCE_EDEVICE);
+      }
+    } else {
+      nnz = g->row_ptr[n];
+    }
+  }
+  st->nnz = nnz;
+  int rc;
+  if ((rc = st->rp[0].ensure((n + 1) * 8)) != MCE_OK) return fail(rc);
+  if ((rc = st->col[0].ensure(std::max<uint64_t>(nnz, 1) * 4)) != MCE_OK) return fail(rc);
+  const hipMemcpyKind kind = g->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (n > 0 && hipMemcpyAsync(st->rp[0].p, g->row_ptr, (n + 1) * 8, kind, s) != hipSuccess) return fail(MCE_EDEVICE);
+  if (nnz > 0 && hipMemcpyAsync(st->col[0].p, g->col, nnz * 4, kind, s) != hipSuccess) return fail(MCE_EDEVICE);
+  if (n == 0) {
+    uint64_t z = 0;
+    if (hipMemcpyAsync(st->rp[0].p, &z, 8, hipMemcpyHostToDevice, s) != hipSuccess) return fail(MCE_EDEVICE);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(MCE_EDEVICE);
+  mce_csr dg{n, st->rp[0].as<uint64_t>(), st->col[0].as<uint32_t>(), 1};
+  mce_result r;
+  rc = mce_static(&dg, MCE_RANK_DEGREE, &st->opts, &r, nullptr, nullptr);
+  if (rc != MCE_OK) return fail(rc);
+  st->count = r.count;
+  st->hash = r.set_hash;
+  if (initial) *initial = r;
+  *out = st;
+  return MCE_OK;
 }
-int imce_add_edges(imce_state*, const uint32_t*, const uint32_t*, uint64_t, int, imce_result*, mce_clique_buf*,
-                   mce_clique_buf*) {
-  set_error("imce_add_edges: not built yet");
-  return MCE_ENOTSUP;
+
+int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                   imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+  if (!st || !out) {
+    set_error("NULL state or result");
+    return MCE_EINVAL;
+  }
+  return add_edges_impl(st, src, dst, rho, on_device, out, new_cl, del_cl);
 }
-int imce_info(const imce_state*, uint64_t*, uint64_t*, uint64_t*, uint64_t*) { return MCE_ENOTSUP; }
-void imce_destroy(imce_state*) {}
+
+int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash) {
+  if (!st) {
+    set_error("NULL state");
+    return MCE_EINVAL;
+  }
+  if (n) *n = st->n;
+  if (nnz) *nnz = st->nnz;
+  if (count) *count = st->count;
+  if (set_hash) *set_hash = st->hash;
+  return MCE_OK;
 }
+
+void imce_destroy(imce_state* st) {
+  if (!st) return;
+  release_state(st);
+  delete st;
+}
+
+}  // extern "C"
