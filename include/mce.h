@@ -72,7 +72,8 @@ typedef enum { MCE_RANK_DEGREE = 0, MCE_RANK_DEGENERACY = 1, MCE_RANK_TRIANGLE =
 typedef enum {
   MCE_SCHED_DEGREE = 0,   /* vertex degree */
   MCE_SCHED_TRIANGLE = 1, /* triangles through the vertex */
-  MCE_SCHED_COST = 2,     /* caller-supplied per-vertex cost (e.g. a learned cost model) */
+  MCE_SCHED_COST = 2,     /* caller-supplied per-vertex float cost, any real value (e.g. a learned
+                             model's predicted log search nodes) */
   MCE_SCHED_ID = 3        /* ascending vertex id */
 } mce_sched;
 
@@ -176,6 +177,36 @@ int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
 int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash);
 
 void imce_destroy(imce_state* st);
+
+/* --- learned cost model (orders the queue only, never changes results) ----
+ * A 4 -> 64 -> 64 -> 1 ReLU MLP from the mce_features columns to log(search
+ * nodes of the vertex's subproblem).  Parameters are one float block of
+ * mce_mlp_param_count() entries, row-major: W1[64][4], b1[64], W2[64][64],
+ * b2[64], w3[64], b3, then mu[4], sigma[4] (inputs are standardised as
+ * (x - mu) / sigma).  All pointers are device memory; n is the number of
+ * vertices (feat is n x 4, row-major). */
+uint32_t mce_mlp_param_count(void);
+/* FP32 prediction: out[i] = MLP(feat[i]). */
+int mce_mlp_forward(const float* params, const float* feat, uint64_t n, float* out, void* hip_stream);
+/* BF16 prediction: weights (params_bf16, from mce_mlp_to_bf16), inputs and
+ * hidden activations rounded to bfloat16, FP32 accumulation; mu/sigma are
+ * read from the FP32 block `params`. */
+int mce_mlp_forward_bf16(const uint16_t* params_bf16, const float* params, const float* feat, uint64_t n, float* out,
+                         void* hip_stream);
+/* Gradient of the mean squared error (1/n) sum (MLP(feat[i]) - target[i])^2
+ * with respect to the trainable parameters (all but mu/sigma) into grad
+ * (mce_mlp_param_count() floats, overwritten) and the loss into loss[0]. */
+int mce_mlp_grad(const float* params, const float* feat, const float* target, uint64_t n, float* grad, float* loss,
+                 void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the trainable
+ * parameters; m and v are zero-initialised moment buffers; step >= 1. */
+int mce_mlp_adam(float* params, float* m, float* v, const float* grad, float lr, uint32_t step, void* hip_stream);
+/* mu/sigma of the parameter block from the feature columns. */
+int mce_mlp_fit_norm(float* params, const float* feat, uint64_t n, void* hip_stream);
+/* Round-to-nearest-even bfloat16 copy of the parameter block. */
+int mce_mlp_to_bf16(const float* params, uint16_t* params_bf16, void* hip_stream);
+/* Training targets: target[i] = log(max(nodes[i], 1)). */
+int mce_mlp_labels(const uint64_t* nodes, uint64_t n, float* target, void* hip_stream);
 
 const char* mce_strerror(int code);
 const char* mce_last_error(void);

@@ -67,7 +67,9 @@ class _ImceResult(ctypes.Structure):
 
 
 EXPORTS = ("mce_static", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_info",
-           "imce_destroy", "mce_strerror", "mce_last_error")
+           "imce_destroy", "mce_strerror", "mce_last_error", "mce_mlp_param_count", "mce_mlp_forward",
+           "mce_mlp_forward_bf16", "mce_mlp_grad", "mce_mlp_adam", "mce_mlp_fit_norm", "mce_mlp_to_bf16",
+           "mce_mlp_labels")
 
 _lib = None
 
@@ -94,6 +96,15 @@ def lib():
         L.imce_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.imce_destroy.argtypes = [ctypes.c_void_p]
+        L.mce_mlp_param_count.restype = ctypes.c_uint32
+        vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+        L.mce_mlp_forward.argtypes = [vp, vp, u64, vp, vp]
+        L.mce_mlp_forward_bf16.argtypes = [vp, vp, vp, u64, vp, vp]
+        L.mce_mlp_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.mce_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_uint32, vp]
+        L.mce_mlp_fit_norm.argtypes = [vp, vp, u64, vp]
+        L.mce_mlp_to_bf16.argtypes = [vp, vp, vp]
+        L.mce_mlp_labels.argtypes = [vp, u64, vp, vp]
         _lib = L
     return _lib
 

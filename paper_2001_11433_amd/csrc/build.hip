@@ -225,9 +225,10 @@ __global__ void k_queue_keys(uint64_t n, const uint64_t* __restrict__ rp, const 
     switch (sched) {
       case MCE_SCHED_TRIANGLE: prim = tri[v]; break;
       case MCE_SCHED_COST: {
-        float c = cost[v];
-        if (!(c > 0.0f)) c = 0.0f;  // NaN and negatives sort last
-        prim = (uint64_t)__float_as_uint(c);
+        // order-preserving map of the float onto 32 bits; NaN sorts last
+        const float c = cost[v];
+        const uint32_t u = __float_as_uint(c);
+        prim = (c != c) ? 0 : (uint64_t)((u & 0x80000000u) ? ~u : (u | 0x80000000u));
         break;
       }
       case MCE_SCHED_ID: prim = 0xFFFFFFFFull - v; break;

@@ -1,0 +1,125 @@
+"""GPU cost-model kernels against the FP64 reference (oracle/mlp.py).
+
+FP32 forward and gradient within FP32 rounding of the FP64 values; the BF16
+kernel within 2e-2 of FP32 on the log scale and within bfloat16 rounding of the
+reference's BF16 forward; bit-exact bfloat16 conversion."""
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import mlp as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_11433_amd as m
+    from paper_2001_11433_amd import costmodel
+    m.lib()
+    return costmodel
+
+
+def _case(seed, n=1000):
+    rng = np.random.default_rng(seed)
+    p = R.init(seed)
+    mu = R.OFFSETS["mu"][0]
+    p[mu:mu + 4] = rng.normal(size=4)
+    p[mu + 4:mu + 8] = rng.uniform(0.5, 2, size=4)
+    X = rng.normal(size=(n, 4)) * 2
+    t = rng.normal(size=n)
+    return p.astype(np.float32), X.astype(np.float32), t.astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_forward_fp32_matches_reference(cm):
+    for seed in range(3):
+        p, X, _ = _case(seed, 1537)
+        model = cm.CostModel(params=p)
+        got = model.predict(_dev(X), bf16=False).cpu().numpy()
+        want = R.forward(p.astype(np.float64), X.astype(np.float64))
+        assert np.allclose(got, want, rtol=1e-4, atol=1e-4)
+
+
+def test_gradient_matches_reference(cm):
+    for seed in range(3):
+        p, X, t = _case(seed, 2000 + 37 * seed)
+        model = cm.CostModel(params=p)
+        g, loss = model.grad(_dev(X), _dev(t))
+        g = g.cpu().numpy().astype(np.float64)
+        want = R.grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+        assert np.linalg.norm(g - want) <= 1e-4 * np.linalg.norm(want)
+        assert abs(loss - R.loss(p.astype(np.float64), X, t)) <= 1e-5 * abs(loss)
+
+
+def test_adam_step_matches_reference(cm):
+    p, X, t = _case(4, 800)
+    model = cm.CostModel(params=p)
+    for step in range(1, 4):
+        g, _ = model.grad(_dev(X), _dev(t))
+        g64 = g.cpu().numpy().astype(np.float64)
+        m0, v0 = model.m.cpu().numpy().astype(np.float64), model.v.cpu().numpy().astype(np.float64)
+        p0 = model.params.cpu().numpy().astype(np.float64)
+        model.adam(1e-2)
+        want, _, _ = R.adam(p0, m0, v0, g64, 1e-2, step)
+        assert np.allclose(model.params.cpu().numpy(), want, atol=2e-6)
+
+
+def test_bf16_conversion_is_exact(cm):
+    import torch
+    p, _, _ = _case(5)
+    model = cm.CostModel(params=p)
+    from paper_2001_11433_amd import lib
+    lib().mce_mlp_to_bf16(model.params.data_ptr(), model.p16.data_ptr(), None)
+    torch.cuda.synchronize()
+    got = (model.p16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(got.astype(np.float64), R.bf16(p))
+
+
+def test_bf16_inference(cm):
+    p, X, _ = _case(6, 3000)
+    model = cm.CostModel(params=p)
+    y16 = model.predict(_dev(X), bf16=True).cpu().numpy().astype(np.float64)
+    y32 = model.predict(_dev(X), bf16=False).cpu().numpy().astype(np.float64)
+    ref16 = R.forward_bf16(p, X)
+    assert np.allclose(y16, ref16, rtol=1e-3, atol=1e-3)
+    assert np.all(np.abs(y16 - y32) <= 2e-2 * np.maximum(1.0, np.abs(y32)))
+
+
+def test_norm_and_labels(cm):
+    import torch
+    rng = np.random.default_rng(1)
+    X = (rng.normal(size=(5000, 4)) * [1, 2, 3, 4] + [5, 6, 7, 8]).astype(np.float32)
+    model = cm.CostModel(params=R.init(0).astype(np.float32))
+    model.fit_norm(_dev(X))
+    q = R.unpack(model.params.cpu().numpy().astype(np.float64))
+    assert np.allclose(q["mu"], X.astype(np.float64).mean(0), rtol=1e-5)
+    assert np.allclose(q["sigma"], X.astype(np.float64).std(0), rtol=1e-4)
+    nodes = torch.tensor([1, 2, 10, 12345678, 0], dtype=torch.int64, device="cuda")
+    lab = cm.labels(nodes).cpu().numpy()
+    assert np.allclose(lab, np.log([1, 2, 10, 12345678, 1]), rtol=1e-6)
+
+
+def test_training_learns_node_counts_and_schedule_is_result_neutral(cm):
+    import paper_2001_11433_amd as m
+    graphs = [gg.rmat(11, seed=s) for s in range(1, 5)]
+    out = cm.train_on_graphs(graphs, "degeneracy", epochs=300, lr=3e-3)
+    losses = out["losses"]
+    assert losses[-1] < 0.5 * losses[0]
+    model = out["model"]
+    held = gg.rmat(11, seed=11)
+    feat, target, base = cm.collect(held, "degeneracy")
+    pred = model.predict(feat)
+    rho = R.spearman(pred.cpu().numpy(), target.cpu().numpy())
+    assert rho > 0.5
+    learned = m.mce_static(held, rank="degeneracy", sched="cost", cost=pred)
+    assert (learned["count"], learned["set_hash"], learned["nodes_total"]) == \
+        (base["count"], base["set_hash"], base["nodes_total"])
