@@ -1,0 +1,107 @@
+"""Autotuner for the persistent enumeration launch.
+
+The tunable knobs change only speed, never results: waves per compute unit
+(how many persistent wavefronts share the work queue) and the donation
+interval (search nodes between checks for idle waves).  Skewed graphs, where
+one subproblem holds most of the work, prefer few, quiet waves; graphs with
+many heavy subproblems prefer full occupancy.  The tuner runs a coordinate
+search (waves first, then interval) and keeps the fastest setting, checking
+that every trial returns the same count and hash.
+
+Results are cached per graph signature (n, m, max degree, degree-sequence
+digest, rank) in a JSON table; `tuning.json` next to this file holds the
+entries measured for the benchmark workloads.
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Dict, Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _as_device_graph, mce_static
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+WAVES = (1, 2, 4, 8, 16)
+INTERVALS = (64, 256, 1024)
+DEFAULT = {"waves_per_cu": 8, "donate_interval": 256}
+
+
+def signature(g, rank: str) -> str:
+    """Stable key of a host graph (graphgen.Graph): sizes plus a degree digest."""
+    deg = np.diff(np.asarray(g.row_ptr, dtype=np.uint64)).astype(np.uint64)
+    h = hashlib.sha1(deg.tobytes()).hexdigest()[:16]
+    return "n%d-m%d-dmax%d-%s-%s" % (g.n, int(g.row_ptr[-1]) // 2, int(deg.max()) if g.n else 0, h, rank)
+
+
+def load_table(path: str = TABLE) -> Dict[str, dict]:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_table(table: Dict[str, dict], path: str = TABLE) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(g, rank: str, path: str = TABLE) -> dict:
+    """Tuned launch settings for `g` if known, else the defaults."""
+    entry = load_table(path).get(signature(g, rank))
+    return dict(entry["best"]) if entry else dict(DEFAULT)
+
+
+def tune(g, rank: str = "degree", sched: str = "degree", cost=None, waves: Sequence[int] = WAVES,
+         intervals: Sequence[int] = INTERVALS, time_limit_s: Optional[float] = None, path: Optional[str] = TABLE,
+         log=None) -> dict:
+    """Coordinate search; returns {"best": {...}, "trials": [...]} and records it."""
+    dg = _as_device_graph(g)
+    trials = []
+    ref = None
+    t_start = time.perf_counter()
+
+    def run(wpc, iv):
+        nonlocal ref
+        r = mce_static(dg, rank=rank, sched=sched, cost=cost, waves_per_cu=wpc, donate_interval=iv)
+        key = (r["count"], r["set_hash"], r["nodes_total"])
+        if ref is None:
+            ref = key
+        elif key != ref:
+            raise RuntimeError("tuning trial changed the result: %r vs %r" % (key, ref))
+        t = r["enum_ms"]
+        trials.append({"waves_per_cu": wpc, "donate_interval": iv, "enum_ms": t})
+        if log:
+            log("tune wpc=%d interval=%d enum_ms=%.1f" % (wpc, iv, t))
+        return t
+
+    def out_of_time():
+        return time_limit_s is not None and time.perf_counter() - t_start > time_limit_s
+
+    mce_static(dg, rank=rank, sched=sched, cost=cost)  # warm the workspace
+    best_iv = DEFAULT["donate_interval"]
+    best = None
+    for wpc in waves:
+        t = run(wpc, best_iv)
+        if best is None or t < best[0]:
+            best = (t, wpc, best_iv)
+        if out_of_time():
+            break
+    for iv in intervals:
+        if iv == best_iv or out_of_time():
+            continue
+        t = run(best[1], iv)
+        if t < best[0]:
+            best = (t, best[1], iv)
+    result = {"best": {"waves_per_cu": best[1], "donate_interval": best[2]}, "enum_ms": best[0], "trials": trials}
+    if path:
+        table = load_table(path)
+        table[signature(g, rank)] = result
+        save_table(table, path)
+    return result

@@ -1,0 +1,62 @@
+"""Autotuner and online serving on the GPU.
+
+The tuner may only change speed: every trial must return the same count and
+hash.  The server runs several sessions concurrently (continuous batching on
+per-session streams); each request's result must equal the result of the
+same batch processed alone, bit for bit."""
+
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_11433_amd as mod
+    mod.lib()
+    return mod
+
+
+def test_tuner_keeps_results_and_records_the_best(m, tmp_path):
+    from paper_2001_11433_amd import tuner
+    g = gg.rmat(11, seed=7)
+    path = str(tmp_path / "tuning.json")
+    out = tuner.tune(g, "degeneracy", waves=(1, 2, 4), intervals=(64, 256), path=path)
+    assert len(out["trials"]) >= 4
+    best = tuner.lookup(g, "degeneracy", path)
+    assert best == out["best"]
+    assert min(t["enum_ms"] for t in out["trials"]) == out["enum_ms"]
+    assert tuner.lookup(gg.rmat(10, seed=1), "degeneracy", path) == tuner.DEFAULT
+
+
+def _sessions():
+    graphs, streams = [], []
+    for s in range(3):
+        g = gg.chung_lu(8000 + 2000 * s, 2.2, 12, seed=s)
+        graphs.append(g)
+        streams.append(gg.edge_stream(g, 6, 50, 400, seed=100 + s))
+    return graphs, streams
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(m):
+    from paper_2001_11433_amd import serving
+    graphs, streams = _sessions()
+    alone = [serving.run_alone(g, st) for g, st in zip(graphs, streams)]
+    for rate in (None, 400.0):
+        mix = serving.replay(graphs, streams, slots=3, rate_hz=rate)
+        assert not mix["errors"]
+        for r in mix["requests"]:
+            want = alone[r.session][r.seq]
+            for k in serving.RESULT_KEYS:
+                assert r.result[k] == want[k], (rate, r.session, r.seq, k)
+        assert mix["max_overlap_sessions"] >= 2
+        assert mix["p99_ms"] >= mix["p50_ms"] > 0
+
