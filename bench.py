@@ -79,6 +79,129 @@ def cpu_baseline(g, rank: str, seconds: float, seed: int = 7):
                       "rank metric and G_v construction are inside the timed region" % (done, g.n, seed, cliques, el)}
 
 
+def _median(xs):
+    return float(np.median(np.asarray(xs, dtype=np.float64)))
+
+
+def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epochs: int = 400):
+    """Queue order by degree, by triangle count and by the MLP's predicted
+    cost (largest first) on held-out R-MAT graphs; ownership rank is
+    degeneracy in every case, so the cliques, their hash and the node counts
+    are identical across orders and only the time moves."""
+    import torch
+    from scipy.stats import spearmanr
+    import graphgen as gg
+    from paper_2001_11433_amd import costmodel, tuner
+
+    fam = "rmat(scale=%d, edge_factor=16, abcd=.57/.19/.19/.05); degeneracy rank" % scale
+    t0 = time.perf_counter()
+    train = [gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s) for s in train_seeds]
+    log("learned_sched: training on %d graphs" % len(train))
+    tr = costmodel.train_on_graphs(train, "degeneracy", epochs=epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    model = tr["model"]
+    out = {"family": fam, "train_seeds": list(train_seeds), "held_out_seeds": list(held_seeds),
+           "train": {"vertices": tr["n_train"], "epochs": epochs, "loss_first": tr["losses"][0],
+                     "loss_last": tr["losses"][-1], "wall_s": train_s,
+                     "kernels": "mce_mlp_grad + mce_mlp_adam (fp32)"},
+           "inference": "mce_features + mce_mlp_forward_bf16", "order": "largest predicted cost first",
+           "held_out": []}
+    tot = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
+    tot_e2e = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
+    cliques_total = 0
+    for s in held_seeds:
+        g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s)
+        dg = m.DeviceGraph.from_graph(g)
+        knobs = tuner.lookup(g, "degeneracy", family="rmat%d" % scale)
+        feat, target, base = costmodel.collect(dg, "degeneracy")
+        pred = model.predict(feat)
+        y, t = pred.cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
+        ref = (base["count"], base["set_hash"], base["nodes_total"])
+        row = {"seed": s, "n": g.n, "m": g.m, "maximal_cliques": base["count"],
+               "set_hash": "%016x" % base["set_hash"], "search_nodes": base["nodes_total"],
+               "mse_log_nodes": float(np.mean((y - t) ** 2)), "spearman": float(spearmanr(y, t)[0]),
+               "launch": knobs}
+        for name in ("degree", "triangle", "learned"):
+            enum, e2e = [], []
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                w0 = time.perf_counter()
+                if name == "learned":
+                    f = m.mce_features(dg)
+                    c = model.predict(f)
+                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, **knobs)
+                else:
+                    r = m.mce_static(dg, rank="degeneracy", sched=name, **knobs)
+                torch.cuda.synchronize()
+                e2e.append((time.perf_counter() - w0) * 1e3)
+                enum.append(r["enum_ms"])
+                if (r["count"], r["set_hash"], r["nodes_total"]) != ref:
+                    raise SystemExit("schedule %s changed the result on seed %d" % (name, s))
+            row[name] = {"enum_ms": _median(enum), "wall_ms": _median(e2e),
+                         "cliques_per_s": base["count"] / (_median(e2e) / 1e3)}
+            tot[name] += _median(enum)
+            tot_e2e[name] += _median(e2e)
+        cliques_total += base["count"]
+        log("learned_sched seed %d: %s" % (s, {k: round(row[k]["wall_ms"], 1) for k in tot}))
+        out["held_out"].append(row)
+    out["cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_e2e.items()}
+    out["gain_vs_degree"] = tot_e2e["degree"] / tot_e2e["learned"]
+    out["gain_vs_triangle"] = tot_e2e["triangle"] / tot_e2e["learned"]
+    out["enum_gain_vs_degree"] = tot["degree"] / tot["learned"]
+    return out
+
+
+def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
+    """Online IMCE: one session, 200 edge-addition batches; closed loop
+    (back to back) repeated, then open-loop Poisson arrivals at fractions of
+    the measured closed-loop capacity.  Every run starts from a fresh state
+    and must end with the same clique count and set hash."""
+    import graphgen as gg
+    from paper_2001_11433_amd import serving as sv, tuner
+    g = gg.chung_lu(500_000, 2.2, 16, seed=0)
+    stream = gg.edge_stream(g, 200, 1000, 5000, seed=2, triadic_fraction=0.5)
+    knobs = tuner.lookup(g, "degree", family="cl500k")
+    out = {"graph": "chung_lu(n=500000, gamma=2.2, mean_degree=16, seed=0); degree rank",
+           "stream": "200 batches, rho ~ U{1000..5000} (seed 2), half uniform non-edges, half triadic closures",
+           "edges": int(sum(len(a) for a, _ in stream)), "sessions": 1, "launch": knobs}
+    finals = set()
+    lat = []
+    walls = []
+    new_del = None
+    for i in range(repeats):
+        r = sv.replay([g], [stream], slots=1, rate_hz=None, **knobs)
+        if r["errors"]:
+            raise SystemExit("serving errors: %r" % r["errors"][:3])
+        reqs = r["requests"]
+        finals.add((reqs[-1].result["count"], reqs[-1].result["set_hash"]))
+        new_del = (sum(q.result["n_new"] for q in reqs), sum(q.result["n_del"] for q in reqs))
+        lat += [q.latency_ms for q in reqs]
+        walls.append(r["wall_s"])
+        log("serving closed loop %d: p50 %.2f p99 %.2f ms, %.1f batches/s" % (i, r["p50_ms"], r["p99_ms"],
+                                                                              r["throughput_batches_per_s"]))
+    cap = len(stream) / _median(walls)
+    out["closed_loop"] = {"repeats": repeats, "samples": len(lat), "p50_ms": sv.nearest_rank(lat, 50),
+                          "p99_ms": sv.nearest_rank(lat, 99), "mean_ms": float(np.mean(lat)),
+                          "batches_per_s": cap, "edges_per_s": out["edges"] / _median(walls)}
+    out["new_cliques_total"], out["subsumed_cliques_total"] = new_del
+    out["open_loop"] = []
+    for load in loads:
+        r = sv.replay([g], [stream], slots=1, rate_hz=load * cap, seed=3, **knobs)
+        if r["errors"]:
+            raise SystemExit("serving errors: %r" % r["errors"][:3])
+        finals.add((r["requests"][-1].result["count"], r["requests"][-1].result["set_hash"]))
+        out["open_loop"].append({"load": load, "rate_hz": load * cap, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                                 "mean_ms": r["mean_ms"]})
+        log("serving open loop %.1f: p50 %.2f p99 %.2f ms" % (load, r["p50_ms"], r["p99_ms"]))
+    if len(finals) != 1:
+        raise SystemExit("serving runs disagree: %r" % finals)
+    cnt, h = finals.pop()
+    out["final_count"], out["final_set_hash"] = cnt, "%016x" % h
+    out["p99_update_ms"] = out["closed_loop"]["p99_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +212,9 @@ def main():
     ap.add_argument("--sched", default="degree")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--learned-scale", type=int, default=14)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -105,15 +231,19 @@ def main():
     log("graph:", {k: info[k] for k in ("n", "m", "max_degree")})
     dg = m.DeviceGraph.from_graph(g)
     stream = torch.cuda.current_stream()
+    from paper_2001_11433_amd import tuner
+    family = {"cl-communities": "cl1m-communities", "rmat": "rmat%d" % args.scale, "cl": "cl500k"}.get(args.workload)
+    knobs = tuner.lookup(g, rank, family=family)
+    log("launch settings:", knobs)
 
     for i in range(args.warmup):
-        r = m.mce_static(dg, rank=rank, sched=args.sched, stream=stream)
+        r = m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **knobs)
         log("warmup %d: %d cliques, enum %.1f ms" % (i, r["count"], r["enum_ms"]))
     torch.cuda.synchronize()
     res = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        res.append(m.mce_static(dg, rank=rank, sched=args.sched, stream=stream))
+        res.append(m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **knobs))
         log("step %d: %d cliques, enum %.1f ms" % (i, res[-1]["count"], res[-1]["enum_ms"]))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -138,11 +268,18 @@ def main():
         "config": {"workload": desc, "n": info["n"], "m": info["m"], "rank": rank, "sched": args.sched,
                    "maximal_cliques": r0["count"], "set_hash": "%016x" % r0["set_hash"],
                    "search_nodes": r0["nodes_total"], "rank_ms": r0["rank_ms"], "build_ms": r0["build_ms"],
-                   "enum_ms": r0["enum_ms"], "donated": r0["donated"]},
+                   "enum_ms": r0["enum_ms"], "donated": r0["donated"], "launch": knobs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / INT32_VALU_PEAK,
                      "traffic": None, "kernel": "k_enum", "ops_per_launch": r0["alg_ops"]},
     }
+    if not args.no_learned:
+        log("learned scheduling ...")
+        out["learned_sched"] = learned_sched(m, args.learned_scale, range(1, 11), (11, 12))
+    if not args.no_serving:
+        log("serving ...")
+        out["serving"] = serving(m)
+        out["p99_update_ms"] = out["serving"]["p99_update_ms"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, rank, args.cpu_seconds)

@@ -52,9 +52,13 @@ def save_table(table: Dict[str, dict], path: str = TABLE) -> None:
     os.replace(tmp, path)
 
 
-def lookup(g, rank: str, path: str = TABLE) -> dict:
-    """Tuned launch settings for `g` if known, else the defaults."""
-    entry = load_table(path).get(signature(g, rank))
+def lookup(g, rank: str, path: str = TABLE, family: Optional[str] = None) -> dict:
+    """Tuned launch settings for `g` if known, else those recorded for its
+    generator family (entries "family:<name>"), else the defaults."""
+    table = load_table(path)
+    entry = table.get(signature(g, rank)) if g is not None else None
+    if entry is None and family is not None:
+        entry = table.get("family:" + family)
     return dict(entry["best"]) if entry else dict(DEFAULT)
 
 
