@@ -136,8 +136,10 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
                 torch.cuda.synchronize()
                 e2e.append((time.perf_counter() - w0) * 1e3)
                 enum.append(r["enum_ms"])
-                if (r["count"], r["set_hash"], r["nodes_total"]) != ref:
-                    raise SystemExit("schedule %s changed the result on seed %d" % (name, s))
+                got = (r["count"], r["set_hash"], r["nodes_total"])
+                if got != ref:
+                    raise SystemExit("schedule %s changed the result on seed %d: (count, hash, nodes) %r, "
+                                     "expected %r" % (name, s, got, ref))
             row[name] = {"enum_ms": _median(enum), "wall_ms": _median(e2e),
                          "cliques_per_s": base["count"] / (_median(e2e) / 1e3)}
             tot[name] += _median(enum)

@@ -133,9 +133,16 @@ constexpr uint32_t kNil = 0xFFFFFFFFu;
 // Donated-task records live in fixed blocks of a pool with a lock-free free
 // list (head = (tag << 32) | block, the tag defeats ABA).  A receiver copies
 // its record out and returns the block at once, so the pool recycles.
+//
+// Ordering: a push writes the block's next link and then swings the head with
+// a release CAS, so the link (and the pusher's last reads of the block) are
+// complete before the block can be popped; a pop reads the head with acquire
+// before it follows the link.  Without these a pop can read a stale link,
+// hand one block to two donors (one record lost, another run twice) or cut
+// the list short.
 __device__ uint32_t pool_pop(const EnumArgs& a) {
   for (int tries = 0; tries < 64; ++tries) {
-    uint64_t old = ld_relaxed(&a.ctl[CTL_FREE]);
+    uint64_t old = __hip_atomic_load(&a.ctl[CTL_FREE], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t idx = (uint32_t)old;
     if (idx == kNil) return kNil;
     const uint32_t nxt = __hip_atomic_load(&a.pool_next[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -147,15 +154,13 @@ __device__ uint32_t pool_pop(const EnumArgs& a) {
   return kNil;
 }
 
-// The caller has finished reading the block: a local wait for its loads is
-// all the ordering a reuse needs (the next owner only writes the block).
+// Returns a block whose contents the caller has finished reading.
 __device__ void pool_push(const EnumArgs& a, uint32_t idx) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   for (;;) {
     uint64_t old = ld_relaxed(&a.ctl[CTL_FREE]);
     __hip_atomic_store(&a.pool_next[idx], (uint32_t)old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t nw = (((old >> 32) + 1) << 32) | idx;
-    if (__hip_atomic_compare_exchange_strong(&a.ctl[CTL_FREE], &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+    if (__hip_atomic_compare_exchange_strong(&a.ctl[CTL_FREE], &old, nw, __ATOMIC_RELEASE, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return;
   }

@@ -125,6 +125,20 @@ def test_donation_stress_keeps_node_counts(m):
     _check(m, g, "degeneracy", donate_interval=1, waves_per_cu=16)
 
 
+def test_repeated_runs_with_heavy_block_recycling(m):
+    # Donation records recycle through a lock-free free list; a wrong ordering
+    # there lost or duplicated whole donated subtrees only now and then, so
+    # the same graph runs several times under different launch shapes.
+    g = gg.rmat(12, seed=12)
+    want = O.mce_parmce(g, "degeneracy", threads=8)
+    dg = m.DeviceGraph.from_graph(g)
+    for wpc, iv in ((2, 1), (16, 1), (2, 64), (8, 4), (16, 16), (4, 1), (1, 1), (16, 2)):
+        got = m.mce_static(dg, rank="degeneracy", waves_per_cu=wpc, donate_interval=iv)
+        assert (got["count"], got["set_hash"], got["nodes_total"]) == (want.count, want.set_hash, want.nodes), \
+            (wpc, iv)
+        assert got["donated"] > 0
+
+
 def test_stack_overflow_retries(m):
     # K_300: 5-word bitsets, too deep for the LDS stack; 4 global frames overflow
     g = gg.complete(300)
