@@ -83,6 +83,7 @@ class Server:
         self.done: List[Request] = []
         self.max_in_flight = 0
         self.max_overlap_sessions = 0
+        self.on_done = None  # called with each finished request, under the lock
 
     def close(self):
         for s in self.states:
@@ -124,6 +125,8 @@ class Server:
             self.in_flight -= 1
             self.mem_in_use -= estimate_bytes(len(req.src))
             self.done.append(req)
+            if self.on_done is not None:
+                self.on_done(req)
             self.lock.notify_all()
 
     def serve(self, total: int, poll_s: float = 0.0005):
@@ -164,9 +167,25 @@ def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.nda
     total = len(reqs)
     t0 = time.perf_counter()
     if rate_hz is None:
-        # closed loop: everything is submitted up front; per-session order and
-        # one-in-flight-per-session make each session issue back to back
+        # closed loop: each session issues its next batch the moment the
+        # previous one completes, so a latency is one batch's own service time
+        # plus any wait for a slot shared with other sessions
+        nxt = {}
         for r in reqs:
+            nxt.setdefault(r.session, []).append(r)
+        for q in nxt.values():
+            q.sort(key=lambda r: r.seq)
+
+        def follow(done_req):
+            q = nxt[done_req.session]
+            if q:
+                r = q.pop(0)
+                r.arrival = time.perf_counter()
+                srv.pending.append(r)
+
+        srv.on_done = follow
+        for q in nxt.values():
+            r = q.pop(0)
             r.arrival = t0
             srv.submit(r)
         done = srv.serve(total)
