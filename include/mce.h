@@ -86,7 +86,14 @@ typedef struct {
   uint32_t waves_per_cu;    /* persistent enumeration waves per compute unit */
   uint32_t donate_interval; /* search nodes between checks for idle waves */
   uint32_t frame_cap;       /* initial DFS frames per wave (grows on demand) */
-  uint32_t reserved[5];
+  /* Root splitting, MCE_SCHED_COST only; 0 = off.  sched_cost[v] is then read
+   * as the natural log of subproblem v's predicted search nodes.  A subproblem
+   * predicted above one wave's share of the total (the total over the launch's
+   * waves) has its root's children dealt out at launch, in up to `split`
+   * chunks of consecutive children (Algorithm 3's child formula makes each
+   * chunk a self-contained task).  Never changes results. */
+  uint32_t split;
+  uint32_t reserved[4];
 } mce_opts;
 
 typedef struct {

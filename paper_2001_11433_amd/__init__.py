@@ -39,8 +39,8 @@ class _Csr(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int), ("validate", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
                 ("sched_cost", ctypes.c_void_p), ("waves_per_cu", ctypes.c_uint32),
-                ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32), ("split", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class _Result(ctypes.Structure):
@@ -166,7 +166,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0, donate_interval=0,
-          frame_cap=0) -> _Opts:
+          frame_cap=0, split=0) -> _Opts:
     o = _Opts()
     o.sched = SCHEDS[sched]
     o.validate = int(bool(validate))
@@ -175,6 +175,7 @@ def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0
     o.waves_per_cu = int(waves_per_cu)
     o.donate_interval = int(donate_interval)
     o.frame_cap = int(frame_cap)
+    o.split = int(split)
     return o
 
 
@@ -184,7 +185,8 @@ def _decode_cliques(off: np.ndarray, vert: np.ndarray, nc: int) -> List[Tuple[in
 
 def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = False, per_vertex: bool = False,
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
-               frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20) -> Dict[str, object]:
+               frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
+               split: int = 0) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
@@ -194,7 +196,7 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     torch = _torch()
     dg = _as_device_graph(g)
     csr = dg.csr()
-    o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap)
+    o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split)
     res = _Result()
     pv = None
     tensors = {}

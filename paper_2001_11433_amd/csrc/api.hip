@@ -31,7 +31,7 @@ namespace {
 // calls on the same device, guarded by one mutex per device.
 struct Workspace {
   DevBuf rp, col, metric, tri, core, coredeg, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
-      gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad;
+      gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad, split, split_total;
   EnumWork ew;
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
@@ -181,10 +181,14 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
 
 }  // namespace
 
+uint32_t enum_grid(const mce_opts& opts) {
+  const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
+  return (uint32_t)cu_count() * wpc;
+}
+
 int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* retries) {
   const mce_opts& opts = *j.opts;
-  const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
-  const uint32_t grid = (uint32_t)cu_count() * wpc;
+  const uint32_t grid = enum_grid(opts);
   uint32_t frame_cap = opts.frame_cap ? opts.frame_cap : 128;
   frame_cap = std::min<uint32_t>(frame_cap, (uint32_t)j.max_p + 2);
   frame_cap = std::max<uint32_t>(frame_cap, 2);
@@ -200,7 +204,7 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     const uint64_t stack_words = (uint64_t)frame_cap * std::max<uint64_t>(j.max_frame + 1, 8);
     MCE_TRY(w.stacks.ensure((uint64_t)grid * stack_words * sizeof(uint64_t)));
     MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap * sizeof(uint64_t), s));
-    MCE_TRY_HIP(launch_queue_fill(j.nq, j.order, w.queue.as<uint64_t>(), s));
+    MCE_TRY_HIP(launch_queue_fill(j.nq, j.order, j.split, w.queue.as<uint64_t>(), s));
     std::memset(ctl, 0, CTL_WORDS * sizeof(uint64_t));
     ctl[CTL_TAIL] = j.nq;
     ctl[CTL_PENDING] = j.nq;
@@ -376,6 +380,14 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   MCE_TRY(ws.iota.ensure(n * sizeof(uint32_t)));
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ws.iota.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
+  const uint32_t* split = nullptr;
+  if (opts.sched == MCE_SCHED_COST && opts.split > 1) {
+    MCE_TRY(ws.split.ensure(n * sizeof(uint32_t)));
+    MCE_TRY(ws.split_total.ensure(sizeof(double)));
+    MCE_TRY_HIP(launch_split_plan(n, b.p, opts.sched_cost, enum_grid(opts), std::min<uint32_t>(opts.split, 0xFFFFu),
+                                  ws.split_total.as<double>(), ws.split.as<uint32_t>(), s));
+    split = ws.split.as<uint32_t>();
+  }
   MCE_TRY_HIP(hipEventRecord(tm.e[2], s));
 
   // --- clique output buffers
@@ -405,6 +417,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   job.gids = ws.gids.as<uint32_t>();
   job.nq = nq;
   job.order = svals;
+  job.split = split;
   job.max_p = max_p;
   job.max_frame = max_frame;
   job.excl = false;

@@ -15,6 +15,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "dev.h"
 #include "internal.h"
 
@@ -240,9 +242,45 @@ __global__ void k_queue_keys(uint64_t n, const uint64_t* __restrict__ rp, const 
   vals[v] = (uint32_t)v;
 }
 
-__global__ void k_queue_fill(uint64_t nq, const uint32_t* __restrict__ vals, uint64_t* queue) {
+// Root task of subproblem v: v + 1, with its chunk count in bits 32..47 when
+// the root is to be split.
+__global__ void k_queue_fill(uint64_t nq, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ split,
+                             uint64_t* queue) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i < nq) queue[i] = (uint64_t)vals[i] + 1;  // root task of subproblem vals[i]
+  if (i >= nq) return;
+  const uint32_t v = vals[i];
+  const uint64_t k = split ? split[v] : 1u;
+  queue[i] = (k > 1 ? (k << 32) : 0) | ((uint64_t)v + 1);
+}
+
+// Predicted work of subproblem v: exp(cost[v]), cost = predicted log search
+// nodes (clamped to a finite range; NaN counts as no work).
+__device__ __forceinline__ double predicted_work(float c) {
+  if (!(c == c)) return 0.0;
+  return exp((double)fminf(fmaxf(c, -80.0f), 80.0f));
+}
+
+__global__ void k_split_total(uint64_t n, const uint32_t* __restrict__ P, const float* __restrict__ cost,
+                              double* total) {
+  double w = 0.0;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+    if (P[v] > 0) w += predicted_work(cost[v]);
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+  if (lane_id() == 0 && w != 0.0) atomicAdd(total, w);
+}
+
+// chunks = ceil(work / share), share = total / waves, at most split_max.
+__global__ void k_split_plan(uint64_t n, const uint32_t* __restrict__ P, const float* __restrict__ cost,
+                             const double* __restrict__ total, uint32_t waves, uint32_t split_max, uint32_t* split) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  uint32_t k = 1;
+  const double share = *total / (double)waves;
+  if (P[v] > 1 && share > 0.0) {
+    const double c = ceil(predicted_work(cost[v]) / share);
+    k = c >= (double)split_max ? split_max : (c > 1.0 ? (uint32_t)c : 1u);
+  }
+  split[v] = k;
 }
 
 }  // namespace
@@ -286,9 +324,22 @@ hipError_t launch_queue_keys(uint64_t n, const uint64_t* rp, const uint32_t* p, 
   return hipGetLastError();
 }
 
-hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, uint64_t* queue, hipStream_t s) {
+hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, const uint32_t* split, uint64_t* queue,
+                             hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_queue_fill, dim3(blocks_for(nq, 256)), dim3(256), 0, s, nq, vals, queue);
+  hipLaunchKernelGGL(k_queue_fill, dim3(blocks_for(nq, 256)), dim3(256), 0, s, nq, vals, split, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_plan(uint64_t n, const uint32_t* p, const float* cost, uint32_t waves, uint32_t split_max,
+                             double* total, uint32_t* split, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(total, 0, sizeof(double), s);
+  if (e != hipSuccess) return e;
+  const uint32_t blocks = std::min<uint32_t>(blocks_for(n, 256), 1024);
+  hipLaunchKernelGGL(k_split_total, dim3(blocks), dim3(256), 0, s, n, p, cost, total);
+  hipLaunchKernelGGL(k_split_plan, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, p, cost, total, waves,
+                     split_max, split);
   return hipGetLastError();
 }
 

@@ -78,6 +78,9 @@ struct Compact {
 __device__ uint64_t claim_task(const EnumArgs& a) {
   uint64_t idx = fetch_add(&a.ctl[CTL_HEAD], 1);
   if (idx >= a.qcap) return 0;
+  // back off while waiting: idle waves must not crowd the memory channel of
+  // the control words that busy waves update
+  uint32_t naps = 1;
   for (;;) {
     uint64_t v = ld_relaxed(&a.queue[idx]);
     if (v) {
@@ -85,7 +88,8 @@ __device__ uint64_t claim_task(const EnumArgs& a) {
       return v;
     }
     if (ld_relaxed(&a.ctl[CTL_PENDING]) == 0) return 0;
-    __builtin_amdgcn_s_sleep(8);
+    for (uint32_t z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(8);
+    if (naps < 16) naps <<= 1;
   }
 }
 
@@ -254,6 +258,64 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
   publish_record(a, blk);
   __threadfence_block();
   return true;
+}
+
+// Deals a root's children out at launch (mce_opts.split): `k` chunks of
+// consecutive children in ascending order.  The highest chunk is queued first
+// and this wave keeps the lowest ones, so a failed reservation simply leaves
+// the rest here.  Each chunk is a continuation of the root whose cand lacks
+// the earlier children and whose fini holds them (Algorithm 3's child
+// formula), so the recursion tree is unchanged.  `fr` is the root frame with
+// its fini words already in place; returns this lane's word of the kept ext.
+template <bool EXCL>
+__device__ uint64_t split_root(const EnumArgs& a, Lds& L, uint64_t* fr, uint32_t F, uint32_t wp, uint32_t s,
+                               uint32_t kroot, uint64_t rP, uint64_t rXp, uint64_t rExt, uint64_t rF, uint64_t zsum,
+                               uint32_t k, bool& can_donate) {
+  const int lane = lane_id();
+  const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp;
+  const uint32_t cc = lane < (int)wp ? (uint32_t)__popcll(rExt) : 0u;
+  const uint32_t incl = wave_incl_scan_u32(cc);
+  const uint32_t total = readlane32(incl, 63);
+  const uint32_t chunks = k < total ? k : total;
+  if (chunks < 2 || R_HDR + F + (kroot + 1) / 2 > kBlockWords) return rExt;
+  const uint32_t size = (total + chunks - 1) / chunks;
+  const uint32_t before = incl - cc;
+  if (EXCL && lane < (int)wp) fr[O_FB + lane] = rF;
+  if (lane == 0) fr[F - 1] = zsum;
+  __threadfence_block();
+  uint64_t keep = rExt;
+  for (uint32_t j = chunks - 1; j >= 1 && can_donate; --j) {
+    const uint32_t lo = j * size;  // rank of the chunk's first child
+    if (lo >= total) continue;
+    // this lane's children of rank < lo
+    const uint32_t r = lo > before ? (lo - before < cc ? lo - before : cc) : 0u;
+    uint64_t below = 0, m = rExt;
+    for (uint32_t z = 0; z < r; ++z) {
+      below |= m & (~m + 1);
+      m &= m - 1;
+    }
+    const uint64_t chunk = keep & ~below;
+    if (ballot(chunk != 0) == 0) continue;
+    const uint32_t blk = reserve_record(a, can_donate);
+    if (blk == kNil) break;
+    uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
+    if (lane == 0) {
+      rec[R_S] = s;
+      rec[R_TYPE] = 0;
+      rec[R_DEPTH] = 0;
+      rec[R_KLEN] = kroot;
+    }
+    if (lane < (int)wp) {
+      rec[R_HDR + lane] = rP & ~below;
+      rec[R_HDR + O_XP + lane] = rXp | below;
+      rec[R_HDR + O_EXT + lane] = chunk;
+    }
+    for (uint32_t q = 3 * wp + lane; q < F; q += kWave) rec[R_HDR + q] = fr[q];
+    for (uint32_t q = lane; q < kroot; q += kWave) ((uint32_t*)(rec + R_HDR + F))[q] = L.kG[q];
+    publish_record(a, blk);
+    keep &= below;
+  }
+  return keep;
 }
 
 // K is maximal: count it, hash it, and optionally write it out.
@@ -484,7 +546,8 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     const bool cont = (ref >> 63) != 0;
     const uint32_t blk = cont ? (uint32_t)(ref & 0xFFFFFFFFULL) : kNil;
     const uint64_t* rec = cont ? a.pool + (uint64_t)blk * kBlockWords : nullptr;
-    const uint32_t s = cont ? (uint32_t)readlane64(rec[R_S], 0) : (uint32_t)(ref - 1);
+    const uint32_t s = cont ? (uint32_t)readlane64(rec[R_S], 0) : (uint32_t)ref - 1u;
+    const uint32_t ksplit = cont ? 1u : (uint32_t)(ref >> 32) & 0xFFFFu;
     const uint32_t rtype = cont ? (uint32_t)readlane64(rec[R_TYPE], 0) : 0u;
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
@@ -715,6 +778,8 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               rExt = lane < (int)wp ? (rP & ~rowP[(uint64_t)lane * nrow + piv]) : 0;
               const uint64_t n_ext = wave_sum_u64((uint64_t)__popcll(rExt));
               acc.tops += 3ULL * s_mem * wv + 2ULL * n_ext * wv + 2ULL * s_mem;
+              if (ksplit > 1 && !cont && d == 0)
+                rExt = split_root<EXCL>(a, L, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
             }
             __syncthreads();
           }

@@ -34,21 +34,23 @@ constexpr uint32_t kBlockWords = 1024;  // one donated-task record
 
 // Control block of one enumeration launch (uint64 words).
 enum {
+  // the words that waves poll or update with atomics during the search sit
+  // on cache lines of their own (16 words = 128 bytes apart)
   CTL_HEAD = 0,      // next queue slot to claim
-  CTL_TAIL = 1,      // next queue slot to fill
-  CTL_PENDING = 2,   // tasks queued or running
-  CTL_POOL = 3,      // task-record pool bump pointer (words)
-  CTL_TICKETS = 4,   // donation tickets handed out
-  CTL_FLAGS = 5,     // bit 0: DFS stack overflow; bit 1: clique counter overflow
-  CTL_DONATED = 6,   // donations that reached the queue
-  CTL_CLQ = 7,       // packed clique-output counter: (cliques << 32) | verts
-  CTL_COUNT = 8,     // maximal cliques
-  CTL_HASH = 9,      // sum of clique hashes
-  CTL_NODES = 10,    // search nodes
-  CTL_OPS = 11,      // algorithmic 32-bit integer operations
-  CTL_FREE = 12,     // free list of pool blocks: (tag << 32) | first free block
-  CTL_DIAG = 16,     // 8 diagnostic counters (see mce_result.diag)
-  CTL_WORDS = 24
+  CTL_TAIL = 16,     // next queue slot to fill
+  CTL_PENDING = 32,  // tasks queued or running
+  CTL_FREE = 48,     // free list of pool blocks: (tag << 32) | first free block
+  CTL_TICKETS = 64,  // donation tickets handed out
+  CTL_CLQ = 80,      // packed clique-output counter: (cliques << 32) | verts
+  // totals, added once per wave at exit (and rare flags)
+  CTL_FLAGS = 96,    // bit 0: DFS stack overflow; bit 1: clique counter overflow
+  CTL_DONATED = 97,  // donations that reached the queue
+  CTL_COUNT = 98,    // maximal cliques
+  CTL_HASH = 99,     // sum of clique hashes
+  CTL_NODES = 100,   // search nodes
+  CTL_OPS = 101,     // algorithmic 32-bit integer operations
+  CTL_DIAG = 104,    // 8 diagnostic counters (see mce_result.diag)
+  CTL_WORDS = 112
 };
 
 // Per-subproblem tables, indexed by subproblem id.
@@ -134,6 +136,7 @@ struct EnumJob {
   const uint32_t* gids;
   uint64_t nq;             // root tasks
   const uint32_t* order;   // their subproblem ids, in queue order
+  const uint32_t* split = nullptr;  // root chunks per subproblem id (1 = run whole); null = none
   uint64_t max_p, max_frame;
   bool excl;               // edge subproblems with excluded edges
   uint64_t *nodes_v, *count_v, *hash_v;
@@ -147,6 +150,9 @@ struct EnumJob {
 // Runs the job (restarting with deeper DFS stacks after an overflow) and
 // copies the control block to `ctl` (CTL_WORDS words).
 int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* retries);
+
+// Persistent waves of an enumeration launch under these options.
+uint32_t enum_grid(const mce_opts& opts);
 
 // rank.hip
 hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s);
@@ -177,7 +183,12 @@ hipError_t launch_build(uint64_t n, const uint64_t* rp, const uint32_t* col, con
 hipError_t launch_queue_keys(uint64_t n, const uint64_t* rp, const uint32_t* p, mce_sched sched,
                              const uint64_t* tri, const float* cost, uint64_t* keys, uint32_t* vals,
                              uint64_t* count, hipStream_t s);
-hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, uint64_t* queue, hipStream_t s);
+hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, const uint32_t* split, uint64_t* queue,
+                             hipStream_t s);
+// Root chunks per subproblem from predicted log search nodes (mce_opts.split).
+// `total` is one double of scratch.
+hipError_t launch_split_plan(uint64_t n, const uint32_t* p, const float* cost, uint32_t waves, uint32_t split_max,
+                             double* total, uint32_t* split, hipStream_t s);
 int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& tmp, size_t& tmp_bytes,
                           hipStream_t s);
 int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint64_t n,

@@ -120,6 +120,29 @@ def test_cost_schedule(m):
     _check(m, g, "degree", sched="cost", cost=cost)
 
 
+@pytest.mark.parametrize("split", [2, 64, 4096])
+def test_root_split_never_changes_results(m, split):
+    # cost = log of the oracle's node counts: the hub's root is far above a
+    # wave's share and is dealt out in up to `split` chunks at launch
+    import torch
+    g = gg.rmat(12, seed=3)
+    want = O.mce_parmce(g, "degeneracy", threads=8)
+    cost = torch.from_numpy(np.log(want.nodes_v.astype(np.float64) + 1.0).astype(np.float32)).cuda()
+    got, _ = _check(m, g, "degeneracy", sched="cost", cost=cost, split=split, waves_per_cu=4)
+    assert got["donated"] > 0
+
+
+def test_root_split_with_extreme_costs(m):
+    # any float is accepted: huge, tiny, NaN and infinite predictions
+    import torch
+    g = gg.rmat(10, seed=6)
+    cost = torch.rand(g.n, device="cuda") * 200.0 - 100.0
+    cost[::7] = float("nan")
+    cost[1::11] = float("inf")
+    cost[2::13] = -float("inf")
+    _check(m, g, "degeneracy", sched="cost", cost=cost, split=1000)
+
+
 def test_donation_stress_keeps_node_counts(m):
     g = gg.rmat(11, seed=1)
     _check(m, g, "degeneracy", donate_interval=1, waves_per_cu=16)
