@@ -93,7 +93,13 @@ typedef struct {
    * chunks of consecutive children (Algorithm 3's child formula makes each
    * chunk a self-contained task).  Never changes results. */
   uint32_t split;
-  uint32_t reserved[4];
+  /* Nodes re-based onto the compact 64 + 64 universe are handed to a second,
+   * low-register kernel with more waves per SIMD.  Its waves per CU (0 =
+   * library default), or inline_compact != 0 to search them in the first
+   * kernel instead.  Neither changes results. */
+  uint32_t compact_waves_per_cu;
+  uint32_t inline_compact;
+  uint32_t reserved[2];
 } mce_opts;
 
 typedef struct {
@@ -113,6 +119,8 @@ typedef struct {
      spent in wide nodes, re-basing, compact nodes and waiting for work, [6]
      cycles spent donating, [7] (tasks << 32) | donation attempts */
   uint64_t diag[8];
+  double compact_ms;    /* device time of the compact kernel (included in enum_ms) */
+  uint64_t handed;      /* re-based nodes it searched (the rest were searched in place) */
 } mce_result;
 
 /* Clique output in CSR form: clique i is vert[off[i] .. off[i+1]), vertices

@@ -40,14 +40,16 @@ class _Opts(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int), ("validate", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
                 ("sched_cost", ctypes.c_void_p), ("waves_per_cu", ctypes.c_uint32),
                 ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32), ("split", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("compact_waves_per_cu", ctypes.c_uint32), ("inline_compact", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class _Result(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("set_hash", ctypes.c_uint64), ("nodes_total", ctypes.c_uint64),
                 ("donated", ctypes.c_uint64), ("subproblems", ctypes.c_uint64), ("max_cand", ctypes.c_uint64),
                 ("alg_ops", ctypes.c_uint64), ("rank_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("enum_ms", ctypes.c_double),
-                ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("diag", ctypes.c_uint64 * 8)]
+                ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("diag", ctypes.c_uint64 * 8),
+                ("compact_ms", ctypes.c_double), ("handed", ctypes.c_uint64)]
 
 
 class _CliqueBuf(ctypes.Structure):
@@ -166,7 +168,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0, donate_interval=0,
-          frame_cap=0, split=0) -> _Opts:
+          frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False) -> _Opts:
     o = _Opts()
     o.sched = SCHEDS[sched]
     o.validate = int(bool(validate))
@@ -176,6 +178,8 @@ def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0
     o.donate_interval = int(donate_interval)
     o.frame_cap = int(frame_cap)
     o.split = int(split)
+    o.compact_waves_per_cu = int(compact_waves_per_cu)
+    o.inline_compact = int(bool(inline_compact))
     return o
 
 
@@ -186,7 +190,7 @@ def _decode_cliques(off: np.ndarray, vert: np.ndarray, nc: int) -> List[Tuple[in
 def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = False, per_vertex: bool = False,
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
-               split: int = 0) -> Dict[str, object]:
+               split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
@@ -196,7 +200,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     torch = _torch()
     dg = _as_device_graph(g)
     csr = dg.csr()
-    o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split)
+    o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split, compact_waves_per_cu,
+              inline_compact)
     res = _Result()
     pv = None
     tensors = {}

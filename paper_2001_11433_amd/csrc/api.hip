@@ -181,6 +181,12 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
 
 }  // namespace
 
+// Handoff arena for the compact kernel: grown to the demand of the previous
+// run, at most kHandRecsMax records in kHandUnitsMax 64-byte units (64 GiB).
+constexpr uint64_t kHandRecsMax = 1ULL << 26;
+constexpr uint64_t kHandUnitsMax = 1ULL << 30;
+constexpr uint32_t kCompactWavesPerCu = 20;
+
 uint32_t enum_grid(const mce_opts& opts) {
   const uint32_t wpc = opts.waves_per_cu ? opts.waves_per_cu : 8;
   return (uint32_t)cu_count() * wpc;
@@ -236,10 +242,57 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     a.cl_vert = j.cl_vert;
     a.cap_cliques = j.cap_cliques;
     a.cap_verts = j.cap_verts;
+    const bool handoff = !opts.inline_compact;
+    uint64_t hand_cap = 0;
+    if (handoff) {
+      // sized to what the previous run asked for; requests beyond the
+      // capacity are searched in place
+      hand_cap = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_recs, 1u << 16), kHandRecsMax);
+      const uint64_t units = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_units, 1u << 20), kHandUnitsMax);
+      MCE_TRY(w.hand.ensure(units * 64));
+      MCE_TRY(w.hand_idx.ensure(hand_cap * sizeof(uint32_t)));
+      a.hand = w.hand.as<uint64_t>();
+      a.hand_units = units;
+      a.hand_idx = w.hand_idx.as<uint32_t>();
+      a.hand_cap = hand_cap;
+    }
     if (j.nq > 0) MCE_TRY_HIP(launch_enum(a, grid, j.excl, s));
     MCE_TRY_HIP(hipMemcpyAsync(ctl, w.ctl.p, CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     MCE_TRY_HIP(hipStreamSynchronize(s));
-    if (!(ctl[CTL_FLAGS] & 1ULL)) return MCE_OK;
+    if (!(ctl[CTL_FLAGS] & 1ULL)) {
+      if (!handoff) return MCE_OK;
+      // second launch: the compact kernel over the handed-off nodes (the
+      // records written form a prefix of the request order)
+      const uint64_t req_recs = ctl[CTL_HAND] >> 32, req_units = ctl[CTL_HAND] & 0xFFFFFFFFULL;
+      w.hand_want_recs = std::max(w.hand_want_recs, req_recs);
+      w.hand_want_units = std::max(w.hand_want_units, req_recs <= kHandRecsMax ? req_units : kHandUnitsMax);
+      const uint64_t nh = ctl[CTL_HANDOK];
+      if (nh == 0) return MCE_OK;
+      const uint64_t qcap2 = nh + max_tickets;
+      if (qcap2 > qcap) MCE_TRY(w.queue.ensure(qcap2 * sizeof(uint64_t)));
+      a.queue = w.queue.as<uint64_t>();
+      a.qcap = qcap2;
+      MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap2 * sizeof(uint64_t), s));
+      MCE_TRY_HIP(launch_queue_fill_hand(nh, a.queue, s));
+      MCE_TRY_HIP(launch_pool_init(w.pool_next.as<uint32_t>(), pool_blocks, s));
+      ctl[CTL_HEAD] = 0;
+      ctl[CTL_TAIL] = nh;
+      ctl[CTL_PENDING] = nh;
+      ctl[CTL_FREE] = 0;
+      ctl[CTL_TICKETS] = 0;
+      MCE_TRY_HIP(hipMemcpyAsync(w.ctl.p, ctl, CTL_WORDS * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      const uint32_t cwpc = opts.compact_waves_per_cu ? opts.compact_waves_per_cu : kCompactWavesPerCu;
+      Timer tm;
+      MCE_TRY(tm.init());
+      MCE_TRY_HIP(hipEventRecord(tm.e[0], s));
+      MCE_TRY_HIP(launch_compact(a, (uint32_t)cu_count() * cwpc, j.excl, s));
+      MCE_TRY_HIP(hipEventRecord(tm.e[1], s));
+      MCE_TRY_HIP(hipMemcpyAsync(ctl, w.ctl.p, CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      MCE_TRY_HIP(hipStreamSynchronize(s));
+      j.hand_ms = tm.ms(0, 1);
+      j.handed = nh;
+      return MCE_OK;
+    }
     if (frame_cap >= j.max_p + 2 || attempt >= 12) {
       set_error("DFS stack overflow at %u frames", frame_cap);
       return MCE_ENOMEM;
@@ -453,6 +506,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   out->donated = ctl[CTL_DONATED];
   out->alg_ops = ctl[CTL_OPS];
   for (int k = 0; k < 8; ++k) out->diag[k] = ctl[CTL_DIAG + k];
+  out->compact_ms = job.hand_ms;
+  out->handed = job.handed;
   out->rank_ms = tm.ms(0, 1);
   out->build_ms = tm.ms(1, 2);
   out->enum_ms = tm.ms(2, 3);

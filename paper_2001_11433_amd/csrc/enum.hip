@@ -53,6 +53,13 @@ struct Lds {
   uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
 };
 
+// LDS of the compact kernel: frames and a K list long enough for a handed-off
+// node (kHandK) plus its compact depth.
+struct LdsC {
+  uint64_t cstk[kCFrames * kCF];
+  uint32_t kG[kHandK + kCFrames + 2];
+};
+
 struct Acc {
   uint64_t tn, tc, th, tops;
 };
@@ -343,8 +350,8 @@ __device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, con
 
 // --- compact path ------------------------------------------------------------
 
-template <bool EXCL>
-__device__ void compact_dfs(const EnumArgs& a, Lds& L, const Compact& c, uint32_t s, uint64_t P, uint64_t Xp,
+template <bool EXCL, class LT>
+__device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t s, uint64_t P, uint64_t Xp,
                             uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand, uint32_t kbase,
                             uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since, const WideCtx* wide,
                             Diag& dg) {
@@ -403,7 +410,9 @@ __device__ void compact_dfs(const EnumArgs& a, Lds& L, const Compact& c, uint32_
         const uint64_t td = now();
         for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
           ++dg.attempts;
-          if (wide && donate_wide(a, L, *wide, can_donate)) continue;
+          if constexpr (sizeof(LT) == sizeof(Lds)) {
+            if (wide && donate_wide(a, L, *wide, can_donate)) continue;
+          }
           uint32_t i = 0;
           uint64_t e = 0;
           for (; i < d; ++i) {
@@ -493,8 +502,8 @@ __device__ void compact_keys(Compact& c) {
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
 }
 
-template <bool EXCL>
-__device__ void compact_from_record(const uint64_t* rec, Compact& c, Lds& L, uint64_t& P, uint64_t& Xp,
+template <bool EXCL, class LT>
+__device__ void compact_from_record(const uint64_t* rec, Compact& c, LT& L, uint64_t& P, uint64_t& Xp,
                                     uint64_t& Xx, uint64_t& ext, uint64_t& zsum, uint64_t& F, uint32_t& klen) {
   const int lane = lane_id();
   const uint64_t hdr = readlane64(rec[R_DEPTH], 0);
@@ -518,6 +527,90 @@ __device__ void compact_from_record(const uint64_t* rec, Compact& c, Lds& L, uin
   ext = readlane64(v, 3);
   zsum = readlane64(v, 4);
   F = readlane64(v, 5);
+}
+
+// Handoff records (one per re-based node, for the compact kernel, which
+// expands and counts it), in 64-byte units of the handoff arena:
+//   word 0  s | np << 32 | nx << 40      word 1  klen
+//   word 2  zsum                         word 3  excluded-edge mask (F)
+//   rowPP[np], rowXP[nx], rowPX[np], (rowEx[np] with exclusion) as u64
+//   gP[np], gX[nx], K[klen] as u32
+// The tie-break keys are recomputed from gP and gX on the other side.
+__device__ __forceinline__ uint32_t hand_words(uint32_t np, uint32_t nx, uint32_t klen, bool excl) {
+  return 4 + 2 * np + nx + (excl ? np : 0) + (np + nx + klen + 1) / 2;
+}
+
+// Reserves and writes one record; false when the arena or the index is full
+// (the request still counts, so the host learns the size it needs).
+template <bool EXCL>
+__device__ bool hand_off(const EnumArgs& a, const Lds& L, const Compact& c, uint32_t gX, uint32_t s, uint64_t F,
+                         uint64_t zsum, uint32_t klen) {
+  const int lane = lane_id();
+  const uint32_t np = c.np, nx = c.nx;
+  const uint32_t units = (hand_words(np, nx, klen, EXCL) + 7) / 8;
+  uint64_t old = 0;
+  if (lane == 0) old = fetch_add(&a.ctl[CTL_HAND], (1ULL << 32) | units);
+  old = readlane64(old, 0);
+  const uint64_t idx = old >> 32, at = old & 0xFFFFFFFFULL;
+  if (idx >= a.hand_cap || at + units > a.hand_units) return false;
+  uint64_t* rec = a.hand + at * 8;
+  if (lane == 0) {
+    rec[0] = (uint64_t)s | ((uint64_t)np << 32) | ((uint64_t)nx << 40);
+    rec[1] = klen;
+    rec[2] = zsum;
+    rec[3] = F;
+    a.hand_idx[idx] = (uint32_t)at;
+    fetch_add(&a.ctl[CTL_HANDOK], 1);
+  }
+  uint64_t* w = rec + 4;
+  if (lane < (int)np) w[lane] = c.rowPP;
+  w += np;
+  if (lane < (int)nx) w[lane] = c.rowXP;
+  w += nx;
+  if (lane < (int)np) w[lane] = c.rowPX;
+  w += np;
+  if (EXCL) {
+    if (lane < (int)np) w[lane] = c.rowEx;
+    w += np;
+  }
+  uint32_t* u = (uint32_t*)w;
+  if (lane < (int)np) u[lane] = c.gP;
+  if (lane < (int)nx) u[np + lane] = gX;
+  for (uint32_t j = lane; j < klen; j += kWave) u[np + nx + j] = L.kG[j];
+  return true;
+}
+
+// Reads a handoff record into compact form (the node still to be expanded).
+template <bool EXCL, class LT>
+__device__ void compact_from_hand(const uint64_t* rec, Compact& c, LT& L, uint64_t& P, uint64_t& Xx, uint64_t& zsum,
+                                  uint64_t& F, uint32_t& klen) {
+  const int lane = lane_id();
+  const uint64_t h = readlane64(rec[0], 0);
+  c.np = (uint32_t)(h >> 32) & 0xFF;
+  c.nx = (uint32_t)(h >> 40) & 0xFF;
+  klen = (uint32_t)readlane64(rec[1], 0);
+  zsum = readlane64(rec[2], 0);
+  F = readlane64(rec[3], 0);
+  const uint32_t np = c.np, nx = c.nx;
+  const uint64_t* w = rec + 4;
+  c.rowPP = lane < (int)np ? w[lane] : 0;
+  w += np;
+  c.rowXP = lane < (int)nx ? w[lane] : 0;
+  w += nx;
+  c.rowPX = lane < (int)np ? w[lane] : 0;
+  w += np;
+  c.rowEx = 0;
+  if (EXCL) {
+    c.rowEx = lane < (int)np ? w[lane] : 0;
+    w += np;
+  }
+  const uint32_t* u = (const uint32_t*)w;
+  c.gP = lane < (int)np ? u[lane] : 0xFFFFFFFFu;
+  c.keyX = lane < (int)nx ? u[np + lane] : 0xFFFFFFFFu;
+  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[np + nx + j];
+  compact_keys(c);
+  P = np == 64 ? ~0ULL : ((1ULL << np) - 1);
+  Xx = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
 }
 
 // --- the kernel ---------------------------------------------------------------
@@ -757,15 +850,24 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
                 }
                 c.rowPX = cPX;
                 c.gP = lane < (int)c.np ? gid[pm] : 0xFFFFFFFFu;
-                c.keyX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
-                compact_keys(c);
-                const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
-                const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
+                const uint32_t gX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
                 const uint64_t Fc = EXCL ? readlane64(cF, 0) : 0;
                 wctx.top = d;
-                dg.t_rebase += now() - tr;
-                compact_dfs<EXCL>(a, L, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc, can_donate,
-                                  since, &wctx, dg);
+                const bool handed = a.hand && kroot + d <= kHandK && hand_off<EXCL>(a, L, c, gX, s, Fc, zsum, kroot + d);
+                if (handed) {
+                  // a handed-off subtree is work done here as far as donation
+                  // pacing goes, else the wide frames would rarely be offered
+                  since += a.donate_interval / 16 + 1;
+                  dg.t_rebase += now() - tr;
+                } else {
+                  c.keyX = gX;
+                  compact_keys(c);
+                  const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
+                  const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
+                  dg.t_rebase += now() - tr;
+                  compact_dfs<EXCL>(a, L, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc, can_donate,
+                                    since, &wctx, dg);
+                }
                 rebased = true;
                 do_pop = true;
             }
@@ -896,9 +998,95 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   }
 }
 
+// The compact kernel: searches handed-off re-based nodes (queue value
+// bit 62 | record) and the compact donations among its own waves (bit 63 |
+// pool block).  Its register footprint is a fraction of k_enum's, so many
+// more waves fit per SIMD to hide the latency of the search's serial chain.
+template <bool EXCL>
+__global__ void __launch_bounds__(64) k_compact(EnumArgs a) {
+  __shared__ LdsC L;
+  const int lane = threadIdx.x;
+  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
+  bool can_donate = a.max_tickets > 0;
+  uint32_t since = 0;
+  Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (;;) {
+    uint64_t ref = 0;
+    const uint64_t tw = now();
+    if (lane == 0) ref = claim_task(a);
+    ref = readlane64(ref, 0);
+    dg.t_idle += now() - tw;
+    if (ref == 0) break;
+    ++dg.tasks;
+    const bool pooled = (ref >> 63) != 0;
+    const uint64_t idx = ref & 0xFFFFFFFFULL;
+    Acc acc = {0, 0, 0, 0};
+    Compact c;
+    uint64_t P, Xp = 0, Xx, ext = 0, zsum, F;
+    uint32_t klen, s;
+    if (pooled) {
+      // a donation among the compact kernel's own waves
+      const uint64_t* rec = a.pool + idx * kBlockWords;
+      s = (uint32_t)readlane64(rec[R_S], 0);
+      compact_from_record<EXCL>(rec, c, L, P, Xp, Xx, ext, zsum, F, klen);
+      __threadfence_block();
+      if (lane == 0) pool_push(a, (uint32_t)idx);
+    } else {
+      const uint64_t* rec = a.hand + (uint64_t)a.hand_idx[idx] * 8;
+      s = (uint32_t)readlane64(rec[0], 0);
+      compact_from_hand<EXCL>(rec, c, L, P, Xx, zsum, F, klen);
+    }
+    const uint32_t p = readlane32(a.sub.p[s], 0);
+    const uint32_t x = readlane32(a.sub.x[s], 0);
+    const uint32_t wv = (p + x + 31) / 32;
+    compact_dfs<EXCL>(a, L, c, s, P, Xp, Xx, ext, F, zsum, !pooled, klen, wv, acc, can_donate, since,
+                      (const WideCtx*)nullptr, dg);
+    if (lane == 0) {
+      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
+      if (a.count_v && acc.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)acc.tc);
+      if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
+      fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
+    }
+    tot_n += acc.tn;
+    tot_c += acc.tc;
+    tot_h += acc.th;
+    tot_ops += acc.tops;
+  }
+  if (lane == 0) {
+    if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
+    if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
+    if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
+    if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 1], (unsigned long long)dg.cnodes);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 4], (unsigned long long)dg.t_compact);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 5], (unsigned long long)dg.t_idle);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 6], (unsigned long long)dg.t_donate);
+    atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 7], (unsigned long long)((dg.tasks << 32) | (dg.attempts & 0xFFFFFFFFULL)));
+  }
+}
+
+__global__ void k_queue_fill_hand(uint64_t nh, uint64_t* queue) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < nh) queue[i] = (1ULL << 62) | i;
+}
+
 __global__ void k_finish_offsets(uint64_t* off, uint64_t nc, uint64_t nv) { off[nc] = nv; }
 
 }  // namespace
+
+hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s) {
+  if (exclusion)
+    hipLaunchKernelGGL(k_compact<true>, dim3(grid), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_compact<false>, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_fill_hand(uint64_t nh, uint64_t* queue, hipStream_t s) {
+  if (nh == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_queue_fill_hand, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, queue);
+  return hipGetLastError();
+}
 
 hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s) {
   const size_t lds = (size_t)kLdsWords * sizeof(uint64_t);

@@ -42,6 +42,8 @@ enum {
   CTL_FREE = 48,     // free list of pool blocks: (tag << 32) | first free block
   CTL_TICKETS = 64,  // donation tickets handed out
   CTL_CLQ = 80,      // packed clique-output counter: (cliques << 32) | verts
+  CTL_HAND = 88,     // handoff requests: (records << 32) | 64-byte units (may exceed the capacity)
+  CTL_HANDOK = 112,  // handoff records written
   // totals, added once per wave at exit (and rare flags)
   CTL_FLAGS = 96,    // bit 0: DFS stack overflow; bit 1: clique counter overflow
   CTL_DONATED = 97,  // donations that reached the queue
@@ -50,7 +52,7 @@ enum {
   CTL_NODES = 100,   // search nodes
   CTL_OPS = 101,     // algorithmic 32-bit integer operations
   CTL_DIAG = 104,    // 8 diagnostic counters (see mce_result.diag)
-  CTL_WORDS = 112
+  CTL_WORDS = 128
 };
 
 // Per-subproblem tables, indexed by subproblem id.
@@ -86,7 +88,15 @@ struct EnumArgs {
   uint64_t* cl_off;      // clique output (nullable)
   uint32_t* cl_vert;
   uint64_t cap_cliques, cap_verts;
+  uint64_t* hand;        // arena of re-based nodes handed to the compact kernel (nullable)
+  uint64_t hand_units;   // its size in 64-byte units
+  uint32_t* hand_idx;    // record index -> first unit
+  uint64_t hand_cap;     // records (at most 2^26, so the packed request counter cannot carry into
+                         // a record that passes both checks)
 };
+
+// A node is handed off only when its K list has at most kHandK vertices.
+constexpr uint32_t kHandK = 64;
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -126,7 +136,8 @@ struct DevBuf {
 // pool, DFS stacks).  Each incremental state owns one, so sessions on
 // different streams never share them.
 struct EnumWork {
-  DevBuf queue, ctl, pool, pool_next, stacks;
+  DevBuf queue, ctl, pool, pool_next, stacks, hand, hand_idx;
+  uint64_t hand_want_recs = 0, hand_want_units = 0;  // what the last run asked for
 };
 
 // One persistent enumeration over a table of subproblems.
@@ -145,6 +156,9 @@ struct EnumJob {
   uint64_t cap_cliques, cap_verts;
   const mce_opts* opts;
   std::function<int(uint32_t attempt, uint64_t* ctl_dev)> before_launch;
+  // written by run_enum: compact-kernel time and the nodes handed to it
+  double hand_ms = 0;
+  uint64_t handed = 0;
 };
 
 // Runs the job (restarting with deeper DFS stacks after an overflow) and
@@ -196,6 +210,9 @@ int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_
 
 // enum.hip
 hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
+// The compact kernel over `nh` handed-off records already in the queue.
+hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
+hipError_t launch_queue_fill_hand(uint64_t nh, uint64_t* queue, hipStream_t s);
 hipError_t launch_finish_offsets(uint64_t* off, uint64_t n_cliques, uint64_t n_verts, hipStream_t s);
 hipError_t launch_pool_init(uint32_t* next, uint64_t blocks, hipStream_t s);
 
