@@ -83,7 +83,7 @@ def _median(xs):
     return float(np.median(np.asarray(xs, dtype=np.float64)))
 
 
-def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epochs: int = 400):
+def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epochs: int = 400, split: int = 1024):
     """Queue order by degree, by triangle count and by the MLP's predicted
     cost (largest first) on held-out R-MAT graphs; ownership rank is
     degeneracy in every case, so the cliques, their hash and the node counts
@@ -105,7 +105,9 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
            "train": {"vertices": tr["n_train"], "epochs": epochs, "loss_first": tr["losses"][0],
                      "loss_last": tr["losses"][-1], "wall_s": train_s,
                      "kernels": "mce_mlp_grad + mce_mlp_adam (fp32)"},
-           "inference": "mce_features + mce_mlp_forward_bf16", "order": "largest predicted cost first",
+           "inference": "mce_features + mce_mlp_forward_bf16",
+           "learned_policy": "queue by predicted cost, largest first; roots predicted above one wave's share "
+                             "split into at most %d chunks at launch" % split,
            "held_out": []}
     tot = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
     tot_e2e = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
@@ -114,6 +116,7 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
         g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s)
         dg = m.DeviceGraph.from_graph(g)
         knobs = tuner.lookup(g, "degeneracy", family="rmat%d" % scale)
+        kw = tuner.launch_kwargs(knobs)
         feat, target, base = costmodel.collect(dg, "degeneracy")
         pred = model.predict(feat)
         y, t = pred.cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
@@ -130,9 +133,9 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
                 if name == "learned":
                     f = m.mce_features(dg)
                     c = model.predict(f)
-                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, **knobs)
+                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, split=split, **kw)
                 else:
-                    r = m.mce_static(dg, rank="degeneracy", sched=name, **knobs)
+                    r = m.mce_static(dg, rank="degeneracy", sched=name, **kw)
                 torch.cuda.synchronize()
                 e2e.append((time.perf_counter() - w0) * 1e3)
                 enum.append(r["enum_ms"])
@@ -164,6 +167,7 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     g = gg.chung_lu(500_000, 2.2, 16, seed=0)
     stream = gg.edge_stream(g, 200, 1000, 5000, seed=2, triadic_fraction=0.5)
     knobs = tuner.lookup(g, "degree", family="cl500k")
+    launch = tuner.launch_kwargs(knobs)
     out = {"graph": "chung_lu(n=500000, gamma=2.2, mean_degree=16, seed=0); degree rank",
            "stream": "200 batches, rho ~ U{1000..5000} (seed 2), half uniform non-edges, half triadic closures",
            "edges": int(sum(len(a) for a, _ in stream)), "sessions": 1, "launch": knobs}
@@ -172,7 +176,7 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     walls = []
     new_del = None
     for i in range(repeats):
-        r = sv.replay([g], [stream], slots=1, rate_hz=None, **knobs)
+        r = sv.replay([g], [stream], slots=1, rate_hz=None, **launch)
         if r["errors"]:
             raise SystemExit("serving errors: %r" % r["errors"][:3])
         reqs = r["requests"]
@@ -189,7 +193,7 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     out["new_cliques_total"], out["subsumed_cliques_total"] = new_del
     out["open_loop"] = []
     for load in loads:
-        r = sv.replay([g], [stream], slots=1, rate_hz=load * cap, seed=3, **knobs)
+        r = sv.replay([g], [stream], slots=1, rate_hz=load * cap, seed=3, **launch)
         if r["errors"]:
             raise SystemExit("serving errors: %r" % r["errors"][:3])
         finals.add((r["requests"][-1].result["count"], r["requests"][-1].result["set_hash"]))
@@ -236,16 +240,17 @@ def main():
     from paper_2001_11433_amd import tuner
     family = {"cl-communities": "cl1m-communities", "rmat": "rmat%d" % args.scale, "cl": "cl500k"}.get(args.workload)
     knobs = tuner.lookup(g, rank, family=family)
+    launch = tuner.launch_kwargs(knobs)
     log("launch settings:", knobs)
 
     for i in range(args.warmup):
-        r = m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **knobs)
+        r = m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **launch)
         log("warmup %d: %d cliques, enum %.1f ms" % (i, r["count"], r["enum_ms"]))
     torch.cuda.synchronize()
     res = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        res.append(m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **knobs))
+        res.append(m.mce_static(dg, rank=rank, sched=args.sched, stream=stream, **launch))
         log("step %d: %d cliques, enum %.1f ms" % (i, res[-1]["count"], res[-1]["enum_ms"]))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -270,10 +275,12 @@ def main():
         "config": {"workload": desc, "n": info["n"], "m": info["m"], "rank": rank, "sched": args.sched,
                    "maximal_cliques": r0["count"], "set_hash": "%016x" % r0["set_hash"],
                    "search_nodes": r0["nodes_total"], "rank_ms": r0["rank_ms"], "build_ms": r0["build_ms"],
-                   "enum_ms": r0["enum_ms"], "donated": r0["donated"], "launch": knobs},
+                   "enum_ms": r0["enum_ms"], "compact_ms": r0["compact_ms"], "handed_off": r0["handed"],
+                   "donated": r0["donated"], "launch": knobs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / INT32_VALU_PEAK,
-                     "traffic": None, "kernel": "k_enum", "ops_per_launch": r0["alg_ops"]},
+                     "traffic": None, "kernel": "k_enum + k_compact (the enumeration: both launches)",
+                     "ops_per_launch": r0["alg_ops"]},
     }
     if not args.no_learned:
         log("learned scheduling ...")

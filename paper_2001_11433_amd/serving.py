@@ -59,16 +59,14 @@ def estimate_bytes(rho: int) -> int:
 
 
 class Server:
-    def __init__(self, graphs: Sequence, slots: int = 4, mem_budget: Optional[int] = None,
-                 waves_per_cu: int = 2, donate_interval: int = 256):
+    def __init__(self, graphs: Sequence, slots: int = 4, mem_budget: Optional[int] = None, **launch):
         torch = _torch()
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in graphs]
         self.states = []
         for g, st in zip(graphs, self.streams):
             with torch.cuda.stream(st):
-                self.states.append(ImceState(g, stream=st, waves_per_cu=waves_per_cu,
-                                             donate_interval=donate_interval))
+                self.states.append(ImceState(g, stream=st, **launch))
         torch.cuda.synchronize()
         self.slots = slots
         if mem_budget is None:
@@ -156,12 +154,12 @@ class Server:
 
 
 def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.ndarray]]], slots: int = 4,
-           rate_hz: Optional[float] = None, seed: int = 0, waves_per_cu: int = 2,
-           donate_interval: int = 256) -> Dict[str, object]:
+           rate_hz: Optional[float] = None, seed: int = 0, **launch) -> Dict[str, object]:
     """Serves every session's batch stream.  rate_hz=None: closed loop (each
     session submits its next batch when the previous one completes); else
-    open loop with Poisson arrivals at rate_hz over all sessions."""
-    srv = Server(graphs, slots=slots, waves_per_cu=waves_per_cu, donate_interval=donate_interval)
+    open loop with Poisson arrivals at rate_hz over all sessions.  `launch`
+    holds ImceState launch settings (waves_per_cu, donate_interval, ...)."""
+    srv = Server(graphs, slots=slots, **launch)
     reqs = [Request(s, k, np.asarray(a, np.uint32), np.asarray(b, np.uint32))
             for s, stream in enumerate(streams) for k, (a, b) in enumerate(stream)]
     total = len(reqs)
@@ -217,10 +215,9 @@ def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.nda
     return out
 
 
-def run_alone(g, stream: Sequence[Tuple[np.ndarray, np.ndarray]], waves_per_cu: int = 2,
-              donate_interval: int = 256) -> List[dict]:
+def run_alone(g, stream: Sequence[Tuple[np.ndarray, np.ndarray]], **launch) -> List[dict]:
     """The same batches, one at a time, on a fresh state (reference results)."""
-    st = ImceState(g, waves_per_cu=waves_per_cu, donate_interval=donate_interval)
+    st = ImceState(g, **launch)
     out = [st.add(a, b) for a, b in stream]
     st.close()
     return out

@@ -26,9 +26,26 @@ import numpy as np
 from . import _as_device_graph, mce_static
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
-WAVES = (1, 2, 4, 8, 16)
-INTERVALS = (64, 256, 1024)
-DEFAULT = {"waves_per_cu": 8, "donate_interval": 256}
+# the compact-search mode and the wave count interact (a skewed graph may
+# want few waves and the search in place), so they are searched as a grid;
+# the donation interval is then searched alone
+GRID = (
+    ("compact", ("inline", 12, 20, 28)),
+    ("waves_per_cu", (2, 4, 8, 16)),
+)
+SPACE = (("donate_interval", (256, 1024, 4096)),)
+DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20}
+
+
+def launch_kwargs(knobs: dict) -> dict:
+    """Tuned knobs as mce_static keyword arguments."""
+    out = {"waves_per_cu": int(knobs.get("waves_per_cu", 0)), "donate_interval": int(knobs.get("donate_interval", 0))}
+    c = knobs.get("compact", DEFAULT["compact"])
+    if c == "inline":
+        out["inline_compact"] = True
+    else:
+        out["compact_waves_per_cu"] = int(c)
+    return out
 
 
 def signature(g, rank: str) -> str:
@@ -62,48 +79,54 @@ def lookup(g, rank: str, path: str = TABLE, family: Optional[str] = None) -> dic
     return dict(entry["best"]) if entry else dict(DEFAULT)
 
 
-def tune(g, rank: str = "degree", sched: str = "degree", cost=None, waves: Sequence[int] = WAVES,
-         intervals: Sequence[int] = INTERVALS, time_limit_s: Optional[float] = None, path: Optional[str] = TABLE,
-         log=None) -> dict:
-    """Coordinate search; returns {"best": {...}, "trials": [...]} and records it."""
+def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, space=SPACE,
+         time_limit_s: Optional[float] = None, path: Optional[str] = TABLE, log=None) -> dict:
+    """Grid over `grid`, then a coordinate search over `space` from the best
+    grid point; returns {"best": knobs, "enum_ms": t, "trials": [...]} and
+    records it under the graph's signature."""
     dg = _as_device_graph(g)
     trials = []
     ref = None
     t_start = time.perf_counter()
 
-    def run(wpc, iv):
+    def run(knobs):
         nonlocal ref
-        r = mce_static(dg, rank=rank, sched=sched, cost=cost, waves_per_cu=wpc, donate_interval=iv)
+        r = mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(knobs))
         key = (r["count"], r["set_hash"], r["nodes_total"])
         if ref is None:
             ref = key
         elif key != ref:
             raise RuntimeError("tuning trial changed the result: %r vs %r" % (key, ref))
         t = r["enum_ms"]
-        trials.append({"waves_per_cu": wpc, "donate_interval": iv, "enum_ms": t})
+        trials.append(dict(knobs, enum_ms=t))
         if log:
-            log("tune wpc=%d interval=%d enum_ms=%.1f" % (wpc, iv, t))
+            log("tune %s enum_ms=%.1f" % (knobs, t))
         return t
 
     def out_of_time():
         return time_limit_s is not None and time.perf_counter() - t_start > time_limit_s
 
-    mce_static(dg, rank=rank, sched=sched, cost=cost)  # warm the workspace
-    best_iv = DEFAULT["donate_interval"]
-    best = None
-    for wpc in waves:
-        t = run(wpc, best_iv)
-        if best is None or t < best[0]:
-            best = (t, wpc, best_iv)
-        if out_of_time():
+    # warm the workspace (and size the handoff arena) with the defaults
+    mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(DEFAULT))
+    best, best_t = None, float("inf")
+    points = [dict(DEFAULT)]
+    for name, values in grid:
+        points = [dict(p, **{name: v}) for p in points for v in values]
+    for k in points:
+        if out_of_time() and best is not None:
             break
-    for iv in intervals:
-        if iv == best_iv or out_of_time():
-            continue
-        t = run(best[1], iv)
-        if t < best[0]:
-            best = (t, best[1], iv)
-    result = {"best": {"waves_per_cu": best[1], "donate_interval": best[2]}, "enum_ms": best[0], "trials": trials}
+        t = run(k)
+        if t < best_t:
+            best, best_t = k, t
+    for name, values in space:
+        for v in values:
+            if v == best.get(name) or out_of_time():
+                continue
+            k = dict(best, **{name: v})
+            t = run(k)
+            if t < best_t:
+                best, best_t = k, t
+    result = {"best": best, "enum_ms": best_t, "trials": trials}
     if path:
         table = load_table(path)
         table[signature(g, rank)] = result

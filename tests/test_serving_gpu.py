@@ -29,7 +29,8 @@ def test_tuner_keeps_results_and_records_the_best(m, tmp_path):
     from paper_2001_11433_amd import tuner
     g = gg.rmat(11, seed=7)
     path = str(tmp_path / "tuning.json")
-    out = tuner.tune(g, "degeneracy", waves=(1, 2, 4), intervals=(64, 256), path=path)
+    out = tuner.tune(g, "degeneracy", grid=(("compact", ("inline", 12)), ("waves_per_cu", (2, 4))),
+                     space=(("donate_interval", (256,)),), path=path)
     assert len(out["trials"]) >= 4
     best = tuner.lookup(g, "degeneracy", path)
     assert best == out["best"]
