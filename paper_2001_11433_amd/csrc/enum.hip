@@ -60,8 +60,12 @@ struct LdsC {
   uint32_t kG[kHandK + kCFrames + 2];
 };
 
+// Per-task tallies.  The algorithmic op count of a node is
+// 3*s*w + 2*|ext|*w + 2*s with w fixed per subproblem, so the task keeps the
+// sums of s and |ext| and multiplies once at the end (ops()).
 struct Acc {
-  uint64_t tn, tc, th, tops;
+  uint64_t tn, tc, th, ssum, esum;
+  __device__ uint64_t ops(uint32_t wv) const { return (3 * ssum + 2 * esum) * wv + 2 * ssum; }
 };
 
 // Per-wave diagnostic counters (see mce_result.diag).
@@ -375,7 +379,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         const uint64_t rpP = readlane64(c.rowPP, row & 63), rpX = readlane64(c.rowXP, row & 63);
         ext = P & ~(row < 64 ? rpP : rpX);
         const uint64_t sm = (uint64_t)__popcll(P) + __popcll(Xp) + __popcll(Xx);
-        acc.tops += 3ULL * sm * wv + 2ULL * (uint64_t)__popcll(ext) * wv + 2ULL * sm;
+        acc.ssum += sm;
+        acc.esum += (uint64_t)__popcll(ext);
       }
     }
     if (!pop && ext) {
@@ -393,8 +398,16 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       P &= ~qb;
       Xp |= qb;
       {
-        const uint64_t v = lane == 0 ? P : lane == 1 ? Xp : lane == 2 ? Xx : lane == 3 ? ext : lane == 4 ? zsum : F;
-        if (lane < 6) L.cstk[d * kCF + lane] = v;
+        // one lane stores the (uniform) frame words
+        if (lane == 0) {
+          uint64_t* f = &L.cstk[d * kCF];
+          f[0] = P;
+          f[1] = Xp;
+          f[2] = Xx;
+          f[3] = ext;
+          f[4] = zsum;
+          f[5] = EXCL ? F : 0;
+        }
       }
       if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
       P &= rq;
@@ -645,7 +658,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;  // subproblem universe in 32-bit words
-    Acc acc = {0, 0, 0, 0};
+    Acc acc = {0, 0, 0, 0, 0};
     bool overflow = false;
 
     if (rtype == 1) {
@@ -879,7 +892,8 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               const uint32_t piv = readlane32(bu, wl);
               rExt = lane < (int)wp ? (rP & ~rowP[(uint64_t)lane * nrow + piv]) : 0;
               const uint64_t n_ext = wave_sum_u64((uint64_t)__popcll(rExt));
-              acc.tops += 3ULL * s_mem * wv + 2ULL * n_ext * wv + 2ULL * s_mem;
+              acc.ssum += s_mem;
+              acc.esum += n_ext;
               if (ksplit > 1 && !cont && d == 0)
                 rExt = split_root<EXCL>(a, L, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
             }
@@ -977,7 +991,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     tot_n += acc.tn;
     tot_c += acc.tc;
     tot_h += acc.th;
-    tot_ops += acc.tops;
+    tot_ops += acc.ops(wv);
   }
   if (lane == 0) {
     if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
@@ -1020,7 +1034,7 @@ __global__ void __launch_bounds__(64) k_compact(EnumArgs a) {
     ++dg.tasks;
     const bool pooled = (ref >> 63) != 0;
     const uint64_t idx = ref & 0xFFFFFFFFULL;
-    Acc acc = {0, 0, 0, 0};
+    Acc acc = {0, 0, 0, 0, 0};
     Compact c;
     uint64_t P, Xp = 0, Xx, ext = 0, zsum, F;
     uint32_t klen, s;
@@ -1050,7 +1064,7 @@ __global__ void __launch_bounds__(64) k_compact(EnumArgs a) {
     tot_n += acc.tn;
     tot_c += acc.tc;
     tot_h += acc.th;
-    tot_ops += acc.tops;
+    tot_ops += acc.ops(wv);
   }
   if (lane == 0) {
     if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
