@@ -99,7 +99,10 @@ typedef struct {
    * kernel instead.  Neither changes results. */
   uint32_t compact_waves_per_cu;
   uint32_t inline_compact;
-  uint32_t reserved[2];
+  /* Order of the handed-off nodes in the compact kernel's queue: 0 = as
+   * produced, 1 = largest candidate set first.  Never changes results. */
+  uint32_t compact_order;
+  uint32_t reserved[1];
 } mce_opts;
 
 typedef struct {

@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
                 ("sched_cost", ctypes.c_void_p), ("waves_per_cu", ctypes.c_uint32),
                 ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32), ("split", ctypes.c_uint32),
                 ("compact_waves_per_cu", ctypes.c_uint32), ("inline_compact", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("compact_order", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 1)]
 
 
 class _Result(ctypes.Structure):
@@ -168,7 +168,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0, donate_interval=0,
-          frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False) -> _Opts:
+          frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False, compact_order=0) -> _Opts:
     o = _Opts()
     o.sched = SCHEDS[sched]
     o.validate = int(bool(validate))
@@ -180,6 +180,7 @@ def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0
     o.split = int(split)
     o.compact_waves_per_cu = int(compact_waves_per_cu)
     o.inline_compact = int(bool(inline_compact))
+    o.compact_order = int(compact_order)
     return o
 
 
@@ -190,7 +191,8 @@ def _decode_cliques(off: np.ndarray, vert: np.ndarray, nc: int) -> List[Tuple[in
 def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = False, per_vertex: bool = False,
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
-               split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False) -> Dict[str, object]:
+               split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False,
+               compact_order: int = 0) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
@@ -201,7 +203,7 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     dg = _as_device_graph(g)
     csr = dg.csr()
     o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split, compact_waves_per_cu,
-              inline_compact)
+              inline_compact, compact_order)
     res = _Result()
     pv = None
     tensors = {}

@@ -273,7 +273,21 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
       a.queue = w.queue.as<uint64_t>();
       a.qcap = qcap2;
       MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap2 * sizeof(uint64_t), s));
-      MCE_TRY_HIP(launch_queue_fill_hand(nh, a.queue, s));
+      const uint32_t* order = nullptr;
+      if (opts.compact_order == 1) {
+        // largest candidate set first (then largest fini)
+        MCE_TRY(w.hkeys.ensure(nh * 8));
+        MCE_TRY(w.hkeys2.ensure(nh * 8));
+        MCE_TRY(w.hvals.ensure(nh * 4));
+        MCE_TRY(w.hvals2.ensure(nh * 4));
+        MCE_TRY_HIP(launch_hand_keys(nh, a.hand, a.hand_idx, w.hkeys.as<uint64_t>(), w.hvals.as<uint32_t>(), s));
+        uint64_t* sk;
+        uint32_t* sv;
+        MCE_TRY(device_sort_desc(w.hkeys.as<uint64_t>(), w.hvals.as<uint32_t>(), w.hkeys2.as<uint64_t>(),
+                                 w.hvals2.as<uint32_t>(), nh, w.sort_tmp, w.sort_bytes, s, &sk, &sv, 16));
+        order = sv;
+      }
+      MCE_TRY_HIP(launch_queue_fill_hand(nh, order, a.queue, s));
       MCE_TRY_HIP(launch_pool_init(w.pool_next.as<uint32_t>(), pool_blocks, s));
       ctl[CTL_HEAD] = 0;
       ctl[CTL_TAIL] = nh;

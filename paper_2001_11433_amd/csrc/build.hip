@@ -359,11 +359,11 @@ int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& 
 }
 
 int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint64_t n, void*& tmp,
-                     size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out) {
+                     size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out, int end_bit) {
   hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
   hipcub::DoubleBuffer<uint32_t> vb(vals, vals_alt);
   size_t need = 0;
-  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, need, kb, vb, (int)n, 0, 64, s));
+  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, need, kb, vb, (int)n, 0, end_bit, s));
   if (need > tmp_bytes) {
     if (tmp) MCE_TRY_HIP(hipFree(tmp));
     tmp = nullptr;
@@ -371,7 +371,7 @@ int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_
     MCE_TRY_HIP(hipMalloc(&tmp, need));
     tmp_bytes = need;
   }
-  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, need, kb, vb, (int)n, 0, 64, s));
+  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, need, kb, vb, (int)n, 0, end_bit, s));
   *keys_out = kb.Current();
   *vals_out = vb.Current();
   return MCE_OK;

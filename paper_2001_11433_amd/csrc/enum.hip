@@ -397,6 +397,19 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       const uint64_t rqx = readlane64(c.rowPX, q);
       P &= ~qb;
       Xp |= qb;
+      if ((P & rq) == 0) {
+        // the child is a leaf (its cand is empty): one node, maximal iff its
+        // fini is empty too; no frame needed
+        ++acc.tn;
+        if (((Xp & rq) | (Xx & rqx)) == 0) {
+          if (a.cl_vert) {
+            if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
+            __syncthreads();  // the K list is read by every lane
+          }
+          emit(a, acc, zsum + readlane64(c.zP, q), kbase + d + 1, L.kG);
+        }
+        continue;
+      }
       {
         // one lane stores the (uniform) frame words
         if (lane == 0) {
@@ -1079,9 +1092,18 @@ __global__ void __launch_bounds__(64) k_compact(EnumArgs a) {
   }
 }
 
-__global__ void k_queue_fill_hand(uint64_t nh, uint64_t* queue) {
+__global__ void k_queue_fill_hand(uint64_t nh, const uint32_t* __restrict__ order, uint64_t* queue) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (i < nh) queue[i] = (1ULL << 62) | i;
+  if (i < nh) queue[i] = (1ULL << 62) | (order ? order[i] : i);
+}
+
+__global__ void k_hand_keys(uint64_t nh, const uint64_t* __restrict__ hand, const uint32_t* __restrict__ hand_idx,
+                            uint64_t* keys, uint32_t* vals) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= nh) return;
+  const uint64_t h = hand[(uint64_t)hand_idx[i] * 8];
+  keys[i] = (((h >> 32) & 0xFF) << 8) | ((h >> 40) & 0xFF);
+  vals[i] = (uint32_t)i;
 }
 
 __global__ void k_finish_offsets(uint64_t* off, uint64_t nc, uint64_t nv) { off[nc] = nv; }
@@ -1096,9 +1118,17 @@ hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_queue_fill_hand(uint64_t nh, uint64_t* queue, hipStream_t s) {
+hipError_t launch_queue_fill_hand(uint64_t nh, const uint32_t* order, uint64_t* queue, hipStream_t s) {
   if (nh == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_queue_fill_hand, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, queue);
+  hipLaunchKernelGGL(k_queue_fill_hand, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, order, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint64_t* keys,
+                            uint32_t* vals, hipStream_t s) {
+  if (nh == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hand_keys, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, hand, hand_idx, keys,
+                     vals);
   return hipGetLastError();
 }
 

@@ -820,9 +820,9 @@ void release_state(imce_state* st) {
                     &st->arena, &st->gids, &st->order, &st->bad, &st->new_off, &st->new_vert, &st->cand_off,
                     &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq,
                     &st->sctl,
-                    &st->del_off, &st->del_vert, &st->ew.queue, &st->ew.ctl, &st->ew.pool, &st->ew.pool_next,
-                    &st->ew.stacks};
+                    &st->del_off, &st->del_vert};
   for (DevBuf* b : bufs) b->release();
+  st->ew.release();
   if (st->scan_tmp) (void)hipFree(st->scan_tmp);
   if (st->sort_tmp) (void)hipFree(st->sort_tmp);
   st->scan_tmp = st->sort_tmp = nullptr;

@@ -136,7 +136,17 @@ struct DevBuf {
 // pool, DFS stacks).  Each incremental state owns one, so sessions on
 // different streams never share them.
 struct EnumWork {
-  DevBuf queue, ctl, pool, pool_next, stacks, hand, hand_idx;
+  DevBuf queue, ctl, pool, pool_next, stacks, hand, hand_idx, hkeys, hkeys2, hvals, hvals2;
+  void* sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+  void release() {
+    for (DevBuf* b : {&queue, &ctl, &pool, &pool_next, &stacks, &hand, &hand_idx, &hkeys, &hkeys2, &hvals, &hvals2})
+      b->release();
+    if (sort_tmp) (void)hipFree(sort_tmp);
+    sort_tmp = nullptr;
+    sort_bytes = 0;
+    hand_want_recs = hand_want_units = 0;
+  }
   uint64_t hand_want_recs = 0, hand_want_units = 0;  // what the last run asked for
 };
 
@@ -206,13 +216,17 @@ hipError_t launch_split_plan(uint64_t n, const uint32_t* p, const float* cost, u
 int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& tmp, size_t& tmp_bytes,
                           hipStream_t s);
 int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint64_t n,
-                     void*& tmp, size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out);
+                     void*& tmp, size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out,
+                     int end_bit = 64);
 
 // enum.hip
 hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
 // The compact kernel over `nh` handed-off records already in the queue.
 hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
-hipError_t launch_queue_fill_hand(uint64_t nh, uint64_t* queue, hipStream_t s);
+hipError_t launch_queue_fill_hand(uint64_t nh, const uint32_t* order, uint64_t* queue, hipStream_t s);
+// Sort keys of the handoff records: candidate count, then fini count.
+hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint64_t* keys,
+                            uint32_t* vals, hipStream_t s);
 hipError_t launch_finish_offsets(uint64_t* off, uint64_t n_cliques, uint64_t n_verts, hipStream_t s);
 hipError_t launch_pool_init(uint32_t* next, uint64_t blocks, hipStream_t s);
 

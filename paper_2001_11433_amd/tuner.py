@@ -30,11 +30,11 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 # want few waves and the search in place), so they are searched as a grid;
 # the donation interval is then searched alone
 GRID = (
-    ("compact", ("inline", 12, 20, 28)),
+    ("compact", ("inline", 8, 12, 20, 28)),
     ("waves_per_cu", (2, 4, 8, 16)),
 )
-SPACE = (("donate_interval", (256, 1024, 4096)),)
-DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20}
+SPACE = (("donate_interval", (256, 1024, 4096, 16384)), ("compact_order", (0, 1)))
+DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20, "compact_order": 0}
 
 
 def launch_kwargs(knobs: dict) -> dict:
@@ -45,6 +45,7 @@ def launch_kwargs(knobs: dict) -> dict:
         out["inline_compact"] = True
     else:
         out["compact_waves_per_cu"] = int(c)
+        out["compact_order"] = int(knobs.get("compact_order", 0))
     return out
 
 
