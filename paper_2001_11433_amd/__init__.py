@@ -274,14 +274,14 @@ class ImceState:
     request, the new and subsumed cliques as sorted lists of sorted tuples."""
 
     def __init__(self, g, stream=None, waves_per_cu: int = 0, donate_interval: int = 0, compact_waves_per_cu: int = 0,
-                 inline_compact: bool = False):
+                 inline_compact: bool = False, compact_order: int = 0):
         torch = _torch()
         self._torch = torch
         dg = _as_device_graph(g)
         self.n = dg.n
         self.stream = stream
         self._opts = _opts("degree", False, stream, None, waves_per_cu, donate_interval, 0, 0, compact_waves_per_cu,
-                           inline_compact)
+                           inline_compact, compact_order)
         h = ctypes.c_void_p()
         res = _Result()
         csr = dg.csr()

@@ -22,3 +22,20 @@ def test_tuner_signature_tracks_the_graph():
 def test_memory_estimate_grows_with_batch():
     from paper_2001_11433_amd.serving import estimate_bytes
     assert estimate_bytes(5000) > estimate_bytes(1000) > 0
+
+
+def test_tuned_knobs_are_accepted_by_every_entry_point():
+    # every knob the tuner can choose maps onto keyword arguments that both
+    # mce_static and ImceState take
+    import inspect
+    import paper_2001_11433_amd as m
+    from paper_2001_11433_amd import tuner
+    static = set(inspect.signature(m.mce_static).parameters)
+    state = set(inspect.signature(m.ImceState.__init__).parameters)
+    points = [dict(tuner.DEFAULT)]
+    for name, values in tuner.GRID + tuner.SPACE:
+        points = [dict(p, **{name: v}) for p in points for v in values][:64]
+    for p in points:
+        kw = set(tuner.launch_kwargs(p))
+        assert kw <= static, kw - static
+        assert kw <= state, kw - state
