@@ -247,8 +247,10 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     if (handoff) {
       // sized to what the previous run asked for; requests beyond the
       // capacity are searched in place
-      hand_cap = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_recs, 1u << 16), kHandRecsMax);
-      const uint64_t units = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_units, 1u << 20), kHandUnitsMax);
+      const uint64_t first = std::max<uint64_t>(j.hand_initial_units, 1u << 20);
+      const uint64_t units = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_units, first), kHandUnitsMax);
+      // a record takes at least one unit
+      hand_cap = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_recs, units), kHandRecsMax);
       MCE_TRY(w.hand.ensure(units * 64));
       MCE_TRY(w.hand_idx.ensure(hand_cap * sizeof(uint32_t)));
       a.hand = w.hand.as<uint64_t>();
@@ -496,6 +498,12 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   job.cap_cliques = cl ? cl->cap_cliques : 0;
   job.cap_verts = cl ? cl->cap_verts : 0;
   job.opts = &opts;
+  if (!opts.inline_compact && ws.ew.hand_want_units == 0) {
+    // a one-off call cannot learn the arena size from an earlier run: take a
+    // quarter of the free device memory (bounded by the arena's maximum)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) job.hand_initial_units = free_b / 4 / 64;
+  }
   job.before_launch = [&](uint32_t attempt, uint64_t* ctl_dev) -> int {
     if (attempt > 0) {
       // results of the aborted run are discarded: reset per-vertex outputs

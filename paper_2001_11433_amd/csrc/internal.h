@@ -166,6 +166,9 @@ struct EnumJob {
   uint64_t cap_cliques, cap_verts;
   const mce_opts* opts;
   std::function<int(uint32_t attempt, uint64_t* ctl_dev)> before_launch;
+  // initial handoff arena in 64-byte units when no earlier run sized it
+  // (0 = a small default)
+  uint64_t hand_initial_units = 0;
   // written by run_enum: compact-kernel time and the nodes handed to it
   double hand_ms = 0;
   uint64_t handed = 0;
