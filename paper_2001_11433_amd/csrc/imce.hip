@@ -36,7 +36,7 @@ struct imce_state {
   mce_opts opts;
   DevBuf bsrc, bdst, keys, idx, keys2, idx2, keep, pos, eu, ev, hkeys, hidx, hkeys2, hidx2, dkeys, didx, dkeys2, didx2,
       addcnt, degw, p, x, words, gwords, off, goff, stats, arena, gids, order, bad, new_off, new_vert, cand_off,
-      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, del_off, del_vert;
+      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, sdefer, del_off, del_vert;
   uint64_t cap_nc = 0, cap_nv = 0, cap_cc = 0, cap_cv = 0;
   EnumWork ew;
   void* scan_tmp = nullptr;
@@ -52,6 +52,9 @@ inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs 
 constexpr uint32_t kSubMaxK = 64;     // largest new clique the subsumed kernel takes
 constexpr uint32_t kSubMaxS = 1024;   // candidate subsets per new clique
 constexpr uint32_t kSubMaxPairs = 256;
+constexpr uint32_t kEdgeRowsPerWave = 16;  // candidate rows one wave of k_edge_rows builds
+constexpr uint32_t kSubFastS = 32;      // the first pass: subsets and batch edges per clique
+constexpr uint32_t kSubFastPairs = 16;
 
 // -- 1. canonicalisation -------------------------------------------------------
 
@@ -228,18 +231,21 @@ __global__ void __launch_bounds__(256) k_edge_rows(uint64_t m, const uint32_t* _
                                                    const uint32_t* __restrict__ gids, const uint64_t* __restrict__ dkeys,
                                                    const uint32_t* __restrict__ didx, uint64_t nd, uint64_t n,
                                                    uint64_t* arena) {
+  // wave (edge e, blockIdx.y): candidates [y * kEdgeRowsPerWave, ...)
   const uint64_t e = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = lane_id();
   if (e >= m) return;
   const uint32_t p = P[e];
-  if (p == 0) return;
+  const uint32_t a0 = blockIdx.y * kEdgeRowsPerWave;
+  if (a0 >= p) return;
+  const uint32_t a1 = a0 + kEdgeRowsPerWave < p ? a0 + kEdgeRowsPerWave : p;
   const uint64_t wp = (p + 63) / 64;
   uint64_t* rowP = arena + off[e];
   uint64_t* excl = rowP + wp * p;
   uint64_t* F0 = excl + (uint64_t)p * wp;
   const uint32_t* g = gids + goff[e];
   const uint32_t u = eu[e], v = ev[e];
-  for (uint32_t a = 0; a < p; ++a) {
+  for (uint32_t a = a0; a < a1; ++a) {
     const uint32_t q = g[a];
     for (uint64_t j = rp[q] + lane; j < rp[q + 1]; j += kWave) {
       const int64_t b = bsearch_u32(g, p, col[j]);
@@ -266,25 +272,36 @@ __global__ void k_iota32(uint64_t n, uint32_t* a) {
 
 // -- 4. subsumed cliques --------------------------------------------------------
 
+template <uint32_t MAXS, uint32_t MAXP>
 struct SubLds {
   uint32_t c[kSubMaxK];
-  uint64_t pairs[kSubMaxPairs];
-  uint64_t S[2][kSubMaxS];
+  uint64_t pairs[MAXP];
+  uint64_t S[2][MAXS];
   uint32_t np, ns;
 };
 
+// Subsumed-clique candidates of the new cliques (or of those listed in
+// `list`, `*nlist` of them).  A clique whose batch edges or subsets exceed
+// this instance's LDS capacities is appended to `defer` (when given) for the
+// large-capacity instance; without `defer` that is an error (flag 2).
 // sctl: [0] packed candidate counter (cands << 32 | verts), [1] flags
-// (1: clique too large, 2: too many subsets or pairs, 4: candidate overflow)
-__global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint64_t* __restrict__ noff,
+// (1: clique too large, 2: too many subsets or pairs, 4: candidate overflow),
+// [2] deferred cliques
+template <uint32_t MAXS, uint32_t MAXP>
+__global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* __restrict__ list,
+                                                 const uint64_t* __restrict__ nlist, uint32_t* defer,
+                                                 const uint64_t* __restrict__ noff,
                                                  const uint32_t* __restrict__ nvert, uint64_t n,
                                                  const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
                                                  const uint64_t* __restrict__ hkeys, uint64_t nh,
                                                  const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* sctl,
                                                  uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
                                                  uint64_t cap_c, uint64_t cap_v) {
-  __shared__ SubLds L;
+  __shared__ SubLds<MAXS, MAXP> L;
   const int lane = threadIdx.x;
-  for (uint64_t ci = blockIdx.x; ci < nnew; ci += gridDim.x) {
+  const uint64_t items = list ? *nlist : nnew;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const uint64_t ci = list ? list[it] : it;
     const uint64_t b0 = noff[ci];
     const uint32_t k = (uint32_t)(noff[ci + 1] - b0);
     if (k > kSubMaxK) {
@@ -304,14 +321,19 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint64_t* 
         const int64_t j2 = bsearch_u32(L.c, k, w);
         if (j2 >= 0) {
           uint32_t slot = atomicAdd(&L.np, 1u);
-          if (slot < kSubMaxPairs) L.pairs[slot] = (1ULL << lane) | (1ULL << j2);
+          if (slot < MAXP) L.pairs[slot] = (1ULL << lane) | (1ULL << j2);
         }
       }
     }
     __syncthreads();
     const uint32_t npairs = L.np;
-    if (npairs > kSubMaxPairs) {
-      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+    if (npairs > MAXP) {
+      if (lane == 0) {
+        if (defer)
+          defer[atomicAdd((unsigned long long*)&sctl[2], 1ULL)] = (uint32_t)ci;
+        else
+          atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      }
       __syncthreads();
       continue;
     }
@@ -333,7 +355,7 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint64_t* 
         const uint32_t cnt = split ? 2u : (keep1 ? 1u : 0u);
         const uint32_t incl = wave_incl_scan_u32(cnt);
         const uint32_t total = readlane32(incl, 63);
-        if (nout + total > kSubMaxS) {
+        if (nout + total > MAXS) {
           overflow = true;
           break;
         }
@@ -351,7 +373,12 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint64_t* 
     }
     __syncthreads();
     if (overflow) {
-      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      if (lane == 0) {
+        if (defer)
+          defer[atomicAdd((unsigned long long*)&sctl[2], 1ULL)] = (uint32_t)ci;
+        else
+          atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      }
       continue;
     }
     // each distinct subset once (first occurrence), then the maximality test in G
@@ -649,7 +676,8 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   MCE_TRY_HIP(hipMemsetAsync(st->arena.p, 0, aw * 8, s));
   hipLaunchKernelGGL(k_edge_gids, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
                      st->ev.as<uint32_t>(), rpn, coln, st->goff.as<uint64_t>(), st->gids.as<uint32_t>());
-  hipLaunchKernelGGL(k_edge_rows, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
+  const uint32_t row_chunks = (uint32_t)std::max<uint64_t>((stats[0] + kEdgeRowsPerWave - 1) / kEdgeRowsPerWave, 1);
+  hipLaunchKernelGGL(k_edge_rows, dim3(blocks_for(m * 64, 256), row_chunks), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
                      st->ev.as<uint32_t>(), rpn, coln, st->p.as<uint32_t>(), st->off.as<uint64_t>(),
                      st->goff.as<uint64_t>(), st->gids.as<uint32_t>(), dk, di, nd, n, st->arena.as<uint64_t>());
   hipLaunchKernelGGL(k_iota32, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, st->order.as<uint32_t>());
@@ -713,12 +741,22 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
     MCE_TRY(st->cand_vert.ensure(st->cap_cv * 4));
     MCE_TRY(st->cand_hash.ensure(st->cap_cc * 8));
     MCE_TRY(st->sctl.ensure(4 * 8));
+    MCE_TRY(st->sdefer.ensure(std::max<uint64_t>(nc_new, 1) * 4));
     MCE_TRY_HIP(hipMemsetAsync(st->sctl.p, 0, 32, s));
     if (nc_new) {
-      const uint32_t grid = (uint32_t)std::min<uint64_t>(nc_new, 8192);
-      hipLaunchKernelGGL(k_subsumed, dim3(grid), dim3(64), 0, s, nc_new, st->new_off.as<uint64_t>(),
-                         st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd, st->sctl.as<uint64_t>(),
+      // most new cliques hold one or two batch edges: a small-LDS pass with
+      // many waves per CU, then the rest with room for kSubMaxS subsets
+      const uint32_t grid = (uint32_t)std::min<uint64_t>(nc_new, 32768);
+      uint64_t* sc = st->sctl.as<uint64_t>();
+      uint32_t* defer = st->sdefer.as<uint32_t>();
+      hipLaunchKernelGGL((k_subsumed<kSubFastS, kSubFastPairs>), dim3(grid), dim3(64), 0, s, nc_new, nullptr, nullptr,
+                         defer, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd, sc,
                          st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(),
+                         st->cap_cc, st->cap_cv);
+      MCE_TRY_HIP(hipGetLastError());
+      hipLaunchKernelGGL((k_subsumed<kSubMaxS, kSubMaxPairs>), dim3(1024), dim3(64), 0, s, nc_new, defer, sc + 2,
+                         nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd,
+                         sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(),
                          st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
     }
@@ -819,7 +857,7 @@ void release_state(imce_state* st) {
                     &st->degw, &st->p, &st->x, &st->words, &st->gwords, &st->off, &st->goff, &st->stats,
                     &st->arena, &st->gids, &st->order, &st->bad, &st->new_off, &st->new_vert, &st->cand_off,
                     &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq,
-                    &st->sctl,
+                    &st->sctl, &st->sdefer,
                     &st->del_off, &st->del_vert};
   for (DevBuf* b : bufs) b->release();
   st->ew.release();

@@ -121,6 +121,31 @@ def test_random_streams_match_oracle_and_recompute(m):
             assert (full["count"], full["set_hash"]) == (got["count"], got["set_hash"])
 
 
+def test_cliques_with_many_batch_edges(m):
+    # A new clique holding many batch edges splits into many subsets: more
+    # than the first subsumed pass keeps in LDS, so it is finished by the
+    # large-capacity pass.  Complete multipartite graphs with all intra-part
+    # edges of some parts added in one batch.
+    for parts, filled in (([3, 3, 3, 3], 2), ([4, 4, 3, 3, 2], 2), ([3, 3, 3, 3, 3], 3)):
+        g = gg.complete_multipartite(parts)
+        starts = np.cumsum([0] + parts[:-1])
+        src, dst = [], []
+        for pi in range(filled):
+            a = starts[pi]
+            for i in range(parts[pi]):
+                for j in range(i + 1, parts[pi]):
+                    src.append(a + i)
+                    dst.append(a + j)
+        st = m.ImceState(g)
+        ost = O.Imce(g)
+        r = st.add(src, dst, cliques=True)
+        want = ost.add(np.asarray(src, np.uint32), np.asarray(dst, np.uint32), cliques=True)
+        assert (r["n_new"], r["n_del"], r["hash_new"], r["hash_del"]) == \
+            (want["n_new"], want["n_del"], want["hash_new"], want["hash_del"]), (parts, filled)
+        assert r["new"] == want["new"] and r["del"] == want["del"]
+        assert (r["count"], r["set_hash"]) == ost.snapshot()
+
+
 def test_powerlaw_stream_counts(m):
     # Chung-Lu base with the configured half-triadic / half-uniform batches
     g = gg.chung_lu(20000, 2.2, 16, seed=3)
