@@ -83,11 +83,12 @@ def _median(xs):
     return float(np.median(np.asarray(xs, dtype=np.float64)))
 
 
-def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epochs: int = 400, split: int = 1024):
-    """Queue order by degree, by triangle count and by the MLP's predicted
-    cost (largest first) on held-out R-MAT graphs; ownership rank is
-    degeneracy in every case, so the cliques, their hash and the node counts
-    are identical across orders and only the time moves."""
+def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 5, epochs: int = 400):
+    """Queue order by degree, by triangle count, by the MLP's predicted cost
+    (largest first) and, as the ceiling of any cost-based order, by the node
+    counts the enumeration itself measured, on held-out R-MAT graphs.
+    Ownership rank is degeneracy in every case, so cliques, hash and node
+    counts are identical across orders and only the time moves."""
     import torch
     from scipy.stats import spearmanr
     import graphgen as gg
@@ -106,11 +107,14 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
                      "loss_last": tr["losses"][-1], "wall_s": train_s,
                      "kernels": "mce_mlp_grad + mce_mlp_adam (fp32)"},
            "inference": "mce_features + mce_mlp_forward_bf16",
-           "learned_policy": "queue by predicted cost, largest first; roots predicted above one wave's share "
-                             "split into at most %d chunks at launch" % split,
-           "held_out": []}
-    tot = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
-    tot_e2e = {"degree": 0.0, "triangle": 0.0, "learned": 0.0}
+           "policies": {"degree": "vertex degree, largest first", "triangle": "triangles, largest first",
+                        "learned": "MLP-predicted log search nodes, largest first",
+                        "measured": "the subproblem's measured search nodes, largest first (ceiling of any "
+                                    "cost-based order)"},
+           "repeats": repeats, "held_out": []}
+    names = ("degree", "triangle", "learned", "measured")
+    tot_enum = dict.fromkeys(names, 0.0)
+    tot_wall = dict.fromkeys(names, 0.0)
     cliques_total = 0
     for s in held_seeds:
         g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s)
@@ -119,41 +123,51 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 3, epoc
         kw = tuner.launch_kwargs(knobs)
         feat, target, base = costmodel.collect(dg, "degeneracy")
         pred = model.predict(feat)
+        measured = target.float().contiguous()
         y, t = pred.cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
         ref = (base["count"], base["set_hash"], base["nodes_total"])
+        inf = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            model.predict(m.mce_features(dg))
+            torch.cuda.synchronize()
+            inf.append((time.perf_counter() - w0) * 1e3)
         row = {"seed": s, "n": g.n, "m": g.m, "maximal_cliques": base["count"],
                "set_hash": "%016x" % base["set_hash"], "search_nodes": base["nodes_total"],
                "mse_log_nodes": float(np.mean((y - t) ** 2)), "spearman": float(spearmanr(y, t)[0]),
-               "launch": knobs}
-        for name in ("degree", "triangle", "learned"):
-            enum, e2e = [], []
+               "inference_ms": _median(inf), "launch": knobs}
+        for name in names:
+            enum, wall = [], []
             for _ in range(repeats):
                 torch.cuda.synchronize()
                 w0 = time.perf_counter()
                 if name == "learned":
-                    f = m.mce_features(dg)
-                    c = model.predict(f)
-                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, split=split, **kw)
+                    c = model.predict(m.mce_features(dg))
+                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, **kw)
+                elif name == "measured":
+                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=measured, **kw)
                 else:
                     r = m.mce_static(dg, rank="degeneracy", sched=name, **kw)
                 torch.cuda.synchronize()
-                e2e.append((time.perf_counter() - w0) * 1e3)
+                wall.append((time.perf_counter() - w0) * 1e3)
                 enum.append(r["enum_ms"])
                 got = (r["count"], r["set_hash"], r["nodes_total"])
                 if got != ref:
                     raise SystemExit("schedule %s changed the result on seed %d: (count, hash, nodes) %r, "
                                      "expected %r" % (name, s, got, ref))
-            row[name] = {"enum_ms": _median(enum), "wall_ms": _median(e2e),
-                         "cliques_per_s": base["count"] / (_median(e2e) / 1e3)}
-            tot[name] += _median(enum)
-            tot_e2e[name] += _median(e2e)
+            row[name] = {"enum_ms": _median(enum), "wall_ms": _median(wall),
+                         "cliques_per_s": base["count"] / (_median(wall) / 1e3)}
+            tot_enum[name] += _median(enum)
+            tot_wall[name] += _median(wall)
         cliques_total += base["count"]
-        log("learned_sched seed %d: %s" % (s, {k: round(row[k]["wall_ms"], 1) for k in tot}))
+        log("learned_sched seed %d: enum ms %s" % (s, {k: round(row[k]["enum_ms"], 1) for k in names}))
         out["held_out"].append(row)
-    out["cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_e2e.items()}
-    out["gain_vs_degree"] = tot_e2e["degree"] / tot_e2e["learned"]
-    out["gain_vs_triangle"] = tot_e2e["triangle"] / tot_e2e["learned"]
-    out["enum_gain_vs_degree"] = tot["degree"] / tot["learned"]
+    out["cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_wall.items()}
+    out["enum_cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_enum.items()}
+    out["gain_vs_degree"] = tot_wall["degree"] / tot_wall["learned"]
+    out["enum_gain_vs_degree"] = tot_enum["degree"] / tot_enum["learned"]
+    out["measured_enum_gain_vs_degree"] = tot_enum["degree"] / tot_enum["measured"]
     return out
 
 
