@@ -498,9 +498,10 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   job.cap_cliques = cl ? cl->cap_cliques : 0;
   job.cap_verts = cl ? cl->cap_verts : 0;
   job.opts = &opts;
-  if (!opts.inline_compact && ws.ew.hand_want_units == 0) {
-    // a one-off call cannot learn the arena size from an earlier run: take a
-    // quarter of the free device memory (bounded by the arena's maximum)
+  if (!opts.inline_compact && nq >= (1u << 17)) {
+    // a large call cannot rely on the demand of earlier (maybe smaller) runs
+    // to size the handoff arena: offer a quarter of the free device memory
+    // (bounded by the arena's maximum; the buffer only grows)
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) job.hand_initial_units = free_b / 4 / 64;
   }

@@ -397,7 +397,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       const uint64_t rqx = readlane64(c.rowPX, q);
       P &= ~qb;
       Xp |= qb;
-      if ((P & rq) == 0) {
+      const uint64_t cP = P & rq;
+      if (cP == 0) {
         // the child is a leaf (its cand is empty): one node, maximal iff its
         // fini is empty too; no frame needed
         ++acc.tn;
@@ -407,6 +408,34 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
             __syncthreads();  // the K list is read by every lane
           }
           emit(a, acc, zsum + readlane64(c.zP, q), kbase + d + 1, L.kG);
+        }
+        continue;
+      }
+      if ((cP & (cP - 1)) == 0) {
+        // the child has one candidate w.  Every t_u of the child is 0 or 1:
+        // if a fini vertex is adjacent to w it is the pivot and ext is empty
+        // (one node); else ext = {w} and the grandchild K+q+w has empty cand
+        // and fini (two nodes, one clique), unless the branch on w is
+        // excluded by an earlier batch edge
+        const uint32_t w = (uint32_t)__builtin_ctzll(cP);
+        const uint64_t rw = readlane64(c.rowPP, w), rwx = readlane64(c.rowPX, w);
+        const uint64_t cXp = Xp & rq, cXx = Xx & rqx;
+        ++acc.tn;
+        const bool blocked = ((cXp & rw) | (cXx & rwx)) != 0;
+        const bool excluded = EXCL && (((F | readlane64(c.rowEx, q)) >> w) & 1ULL);
+        // the child's pivot step, as the op count of an expanded node
+        acc.ssum += 1 + (uint64_t)__popcll(cXp) + (uint64_t)__popcll(cXx);
+        acc.esum += blocked ? 0u : 1u;
+        if (!blocked && !excluded) {
+          ++acc.tn;
+          if (a.cl_vert) {
+            if (lane == 0) {
+              L.kG[kbase + d] = readlane32(c.gP, q);
+              L.kG[kbase + d + 1] = readlane32(c.gP, w);
+            }
+            __syncthreads();  // the K list is read by every lane
+          }
+          emit(a, acc, zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kbase + d + 2, L.kG);
         }
         continue;
       }
@@ -423,7 +452,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         }
       }
       if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
-      P &= rq;
+      P = cP;
       Xp &= rq;
       Xx &= rqx;
       if (EXCL) F |= readlane64(c.rowEx, q);
