@@ -222,6 +222,45 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     return out
 
 
+def calibrate_copy(gib: int = 1, reps: int = 5):
+    """A plain device-to-device copy of a known size, for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
+    import torch
+    n = gib << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    x.fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "reps": reps}), flush=True)
+
+
+def kernel_sources_digest() -> str:
+    """Digest of the search kernels' sources, to tie measured counters to a
+    kernel version."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("enum.hip", "internal.h", "dev.h", "api.hip"):
+        with open(os.path.join(ROOT, "paper_2001_11433_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(ops_per_launch):
+    """HBM bytes per call of the search from the committed counter summary,
+    or None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_cl1m_communities_degree.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources") != kernel_sources_digest():
+        return None
+    return t.get("bytes_per_call")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,7 +274,12 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--learned-scale", type=int, default=14)
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--print-digest", action="store_true", help="print the search kernels' source digest and exit")
     args = ap.parse_args()
+    if args.print_digest:
+        print(kernel_sources_digest())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
               file=sys.stderr)
@@ -245,6 +289,9 @@ def main():
     import paper_2001_11433_amd as m
     if not torch.cuda.is_available():
         raise SystemExit("no GPU")
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     log("generating workload", args.workload)
     g, rank, desc = make_workload(args.workload, args.scale)
     info = g.describe()
@@ -293,7 +340,9 @@ def main():
                    "donated": r0["donated"], "launch": knobs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / INT32_VALU_PEAK,
-                     "traffic": None, "kernel": "k_enum + k_compact (the enumeration: both launches)",
+                     "traffic": measured_traffic(r0["alg_ops"]),
+                     "traffic_unit": "bytes per call (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)",
+                     "kernel": "k_enum + k_compact (the enumeration: both launches)",
                      "ops_per_launch": r0["alg_ops"]},
     }
     if not args.no_learned:
