@@ -1,0 +1,116 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (the tuned table).
+
+The oracle cannot enumerate these graphs whole in test time, so:
+  * the 1M-vertex Chung-Lu + communities graph: the per-subproblem triples
+    (search nodes, cliques, clique-set hash) of a seeded sample of vertices,
+    plus the heaviest subproblems, against the oracle's ParMCE on the same
+    vertices; totals against the sums of the per-subproblem triples;
+  * R-MAT scale 18: rank metrics (degree, core number, triangles) of every
+    vertex against the oracle (its enumeration is far beyond reach);
+  * the 500k-vertex Chung-Lu stream: sampled new and subsumed cliques checked
+    against the definition of the two sets, and the running count and hash
+    against a fresh enumeration of the updated graph.
+"""
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_11433_amd as mod
+    mod.lib()
+    return mod
+
+
+def _u64(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def test_cl1m_communities_sampled_subproblems(m):
+    from paper_2001_11433_amd import tuner
+    g = gg.plant_communities(gg.chung_lu(1_000_000, 2.1, 20, seed=0), count=500, smin=30, smax=80, p=0.9, seed=1)
+    kw = tuner.launch_kwargs(tuner.lookup(g, "degree", family="cl1m-communities"))
+    got = m.mce_static(g, rank="degree", per_vertex=True, **kw)
+    nodes, count, hsh = _u64(got["nodes_v"]), _u64(got["count_v"]), _u64(got["hash_v"])
+    # totals are the sums of the per-subproblem triples (mod 2^64 for the hash)
+    assert int(count.sum()) == got["count"]
+    assert int(nodes.sum()) == got["nodes_total"]
+    assert int(np.add.reduce(hsh, dtype=np.uint64)) == got["set_hash"]
+    # a seeded uniform sample plus the heaviest subproblems the oracle finishes
+    # in seconds (the very heaviest take it minutes each)
+    rng = np.random.default_rng(11)
+    order = np.argsort(nodes)
+    heavy = order[nodes[order] <= 5_000_000][-12:]
+    sample = np.unique(np.concatenate([rng.choice(g.n, 384, replace=False), heavy])).astype(np.uint32)
+    want = O.mce_parmce(g, "degree", verts=sample, threads=8)
+    assert np.array_equal(nodes[sample], want.nodes_v)
+    assert np.array_equal(count[sample], want.count_v)
+    assert np.array_equal(hsh[sample], want.hash_v)
+
+
+@pytest.mark.parametrize("rank", ["degree", "degeneracy", "triangle"])
+def test_rmat18_rank_metrics(m, rank):
+    g = gg.rmat(18, 16, 0.57, 0.19, 0.19, seed=0)
+    got = m.mce_rank_metric(g, rank).cpu().numpy().astype(np.uint64)
+    want = O.rank_metric(g, rank)
+    assert np.array_equal(got, want)
+
+
+def _adj_sets(g):
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col)
+    return lambda v: col[rp[v]:rp[v + 1]]
+
+
+def _is_clique(nb, c):
+    return all(np.isin(np.array(c[i + 1:]), nb(c[i])).all() for i in range(len(c) - 1))
+
+
+def _is_maximal(nb, c):
+    # no vertex outside c is adjacent to all of c
+    common = set(nb(c[0]).tolist())
+    for v in c[1:]:
+        common &= set(nb(v).tolist())
+        if not common:
+            return True
+    return not (common - set(c))
+
+
+def test_cl500k_stream_sampled_cliques_and_recompute(m):
+    from paper_2001_11433_amd import tuner
+    g = gg.chung_lu(500_000, 2.2, 16, seed=0)
+    stream = gg.edge_stream(g, 200, 1000, 5000, seed=2, triadic_fraction=0.5)
+    kw = tuner.launch_kwargs(tuner.lookup(g, "degree", family="cl500k"))
+    st = m.ImceState(g, **kw)
+    rng = np.random.default_rng(5)
+    cur = g
+    for b in range(3):
+        src, dst = stream[b]
+        r = st.add(src, dst, cliques=True, cap_cliques=1 << 20, cap_verts=1 << 24)
+        new_g = gg.add_edges(cur, src, dst)
+        old_nb, new_nb = _adj_sets(cur), _adj_sets(new_g)
+        batch = {(min(int(a), int(c)), max(int(a), int(c))) for a, c in zip(src, dst)}
+        assert len(r["new"]) == r["n_new"] and len(r["del"]) == r["n_del"]
+        for i in rng.choice(len(r["new"]), min(300, len(r["new"])), replace=False):
+            c = r["new"][i]
+            assert _is_clique(new_nb, c) and _is_maximal(new_nb, c)
+            assert any((c[x], c[y]) in batch for x in range(len(c)) for y in range(x + 1, len(c)))
+        for i in rng.choice(len(r["del"]), min(300, len(r["del"])), replace=False):
+            c = r["del"][i]
+            assert _is_clique(old_nb, c) and _is_maximal(old_nb, c)
+            assert not _is_maximal(new_nb, c)
+        # the incremental count and hash equal a fresh enumeration of G + H
+        full = m.mce_static(new_g, rank="degree", **kw)
+        assert (full["count"], full["set_hash"]) == (r["count"], r["set_hash"]), b
+        cur = new_g
+    st.close()
