@@ -176,6 +176,9 @@ typedef struct {
   uint64_t hash_new, hash_del; /* H(Lambda_new), H(Lambda_del) */
   uint64_t count, set_hash;    /* |C(G+H)| and H(C(G+H)) after the batch */
   double new_ms, sub_ms, ms;   /* device time: new cliques, subsumed cliques, whole batch */
+  uint64_t nodes;              /* search nodes of the batch's edge subproblems */
+  uint64_t handed;             /* re-based nodes searched by the compact kernel */
+  double compact_ms;           /* device time of the compact kernel (inside new_ms) */
 } imce_result;
 
 /* Copies `g` to state-owned device memory and enumerates C(g) once (degree

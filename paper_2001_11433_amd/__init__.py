@@ -65,7 +65,8 @@ class _PerVertex(ctypes.Structure):
 class _ImceResult(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("n_applied", "n_skipped", "n_new", "n_del", "hash_new", "hash_del", "count", "set_hash")] + \
-               [("new_ms", ctypes.c_double), ("sub_ms", ctypes.c_double), ("ms", ctypes.c_double)]
+               [("new_ms", ctypes.c_double), ("sub_ms", ctypes.c_double), ("ms", ctypes.c_double),
+                ("nodes", ctypes.c_uint64), ("handed", ctypes.c_uint64), ("compact_ms", ctypes.c_double)]
 
 
 EXPORTS = ("mce_static", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_info",

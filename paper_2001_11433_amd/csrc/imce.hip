@@ -52,7 +52,8 @@ inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs 
 constexpr uint32_t kSubMaxK = 64;     // largest new clique the subsumed kernel takes
 constexpr uint32_t kSubMaxS = 1024;   // candidate subsets per new clique
 constexpr uint32_t kSubMaxPairs = 256;
-constexpr uint32_t kEdgeRowsPerWave = 16;  // candidate rows one wave of k_edge_rows builds
+constexpr uint32_t kEdgeRowsPerWave = 16;
+constexpr uint64_t kStateHandUnits = 1ULL << 24;  // first handoff arena of a state: 1 GiB  // candidate rows one wave of k_edge_rows builds
 constexpr uint32_t kSubFastS = 32;      // the first pass: subsets and batch edges per clique
 constexpr uint32_t kSubFastPairs = 16;
 
@@ -711,7 +712,11 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
     job.cap_cliques = st->cap_nc;
     job.cap_verts = st->cap_nv;
     job.opts = &st->opts;
+    job.hand_initial_units = kStateHandUnits;
     MCE_TRY(run_enum(job, st->ew, s, ctl, nullptr));
+    res->nodes = ctl[CTL_NODES];
+    res->handed = job.handed;
+    res->compact_ms = job.hand_ms;
     if (ctl[CTL_FLAGS] & 2ULL) {
       set_error("new cliques exceed 2^32 vertices or a clique exceeds the supported size");
       return MCE_ENOTSUP;
