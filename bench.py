@@ -281,7 +281,7 @@ def main():
         print(kernel_sources_digest())
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

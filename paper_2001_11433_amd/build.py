@@ -21,7 +21,7 @@ ARCH = os.environ.get("MCE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
-    # no packed-FP32 instruction selection
+    # no packed-FP32 instruction selection: some of its forms have given wrong results on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
