@@ -180,7 +180,7 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     from paper_2001_11433_amd import serving as sv, tuner
     g = gg.chung_lu(500_000, 2.2, 16, seed=0)
     stream = gg.edge_stream(g, 200, 1000, 5000, seed=2, triadic_fraction=0.5)
-    knobs = tuner.lookup(g, "degree", family="cl500k")
+    knobs = tuner.lookup_imce(g, family="cl500k")
     launch = tuner.launch_kwargs(knobs)
     out = {"graph": "chung_lu(n=500000, gamma=2.2, mean_degree=16, seed=0); degree rank",
            "stream": "200 batches, rho ~ U{1000..5000} (seed 2), half uniform non-edges, half triadic closures",

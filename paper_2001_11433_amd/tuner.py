@@ -23,7 +23,7 @@ from typing import Dict, Iterable, Optional, Sequence
 
 import numpy as np
 
-from . import _as_device_graph, mce_static
+from . import ImceState, _as_device_graph, mce_static
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 # the compact-search mode and the wave count interact (a skewed graph may
@@ -131,5 +131,72 @@ def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, s
     if path:
         table = load_table(path)
         table[signature(g, rank)] = result
+        save_table(table, path)
+    return result
+
+
+# incremental step: small batches favour short donation intervals and few waves
+IMCE_SPACE = (
+    ("donate_interval", (16, 64, 256, 1024)),
+    ("compact", ("inline", 4, 8, 20, 28)),
+    ("waves_per_cu", (1, 2, 4, 8)),
+)
+
+
+def lookup_imce(g, path: str = TABLE, family: Optional[str] = None) -> dict:
+    """Tuned launch settings of the incremental step for `g` (or its family
+    entry "family:<name>"), else the static search's settings."""
+    table = load_table(path)
+    entry = table.get(signature(g, "degree") + "-imce")
+    if entry is None and family is not None:
+        entry = table.get("family:" + family + "-imce")
+    return dict(entry["best"]) if entry else lookup(g, "degree", path, family)
+
+
+def tune_imce(g, batches, start: Optional[dict] = None, space=IMCE_SPACE, path: Optional[str] = TABLE,
+              key: Optional[str] = None, log=None) -> dict:
+    """Coordinate search of the launch knobs of the incremental step by the
+    mean device time of `batches` (each trial replays them on a fresh state,
+    after one untimed batch); every trial must report the same batch
+    results.  Recorded under `key` (default: the graph signature + "-imce")."""
+    import torch
+    trials = []
+    ref = None
+
+    def run(knobs):
+        nonlocal ref
+        st = ImceState(g, **launch_kwargs(knobs))
+        out, ms = [], []
+        for i, (a, b) in enumerate(batches):
+            torch.cuda.synchronize()
+            r = st.add(a, b)
+            out.append((r["n_new"], r["n_del"], r["hash_new"], r["hash_del"]))
+            if i:
+                ms.append(r["ms"])
+        st.close()
+        if ref is None:
+            ref = out
+        elif out != ref:
+            raise RuntimeError("tuning trial changed the batch results")
+        t = float(np.mean(ms)) if ms else 0.0
+        trials.append(dict(knobs, mean_ms=t))
+        if log:
+            log("tune_imce %s mean_ms=%.2f" % (knobs, t))
+        return t
+
+    best = dict(start or DEFAULT)
+    best_t = run(best)
+    for name, values in space:
+        for v in values:
+            if v == best.get(name):
+                continue
+            k = dict(best, **{name: v})
+            t = run(k)
+            if t < best_t:
+                best, best_t = k, t
+    result = {"best": best, "mean_ms": best_t, "trials": trials}
+    if path:
+        table = load_table(path)
+        table[key or signature(g, "degree") + "-imce"] = result
         save_table(table, path)
     return result

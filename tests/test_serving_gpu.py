@@ -38,6 +38,17 @@ def test_tuner_keeps_results_and_records_the_best(m, tmp_path):
     assert tuner.lookup(gg.rmat(10, seed=1), "degeneracy", path) == tuner.DEFAULT
 
 
+def test_incremental_tuner_keeps_results(m, tmp_path):
+    from paper_2001_11433_amd import tuner
+    g = gg.chung_lu(6000, 2.2, 12, seed=9)
+    batches = gg.edge_stream(g, 4, 50, 300, seed=10)
+    path = str(tmp_path / "tuning.json")
+    space = (("donate_interval", (64,)), ("compact", ("inline",)))
+    out = tuner.tune_imce(g, batches, space=space, path=path, key="k")
+    assert len(out["trials"]) == 3
+    assert tuner.load_table(path)["k"]["best"] == out["best"]
+
+
 def _sessions():
     graphs, streams = [], []
     for s in range(3):
