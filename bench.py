@@ -214,6 +214,20 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
         out["open_loop"].append({"load": load, "rate_hz": load * cap, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
                                  "mean_ms": r["mean_ms"]})
         log("serving open loop %.1f: p50 %.2f p99 %.2f ms" % (load, r["p50_ms"], r["p99_ms"]))
+    # two sessions (the same graph, two streams) sharing the GPU, closed loop:
+    # a batch of one session is admitted while the other's is on the device
+    stream2 = gg.edge_stream(g, 200, 1000, 5000, seed=4, triadic_fraction=0.5)
+    r = sv.replay([g, g], [stream, stream2], slots=2, rate_hz=None, **launch)
+    if r["errors"]:
+        raise SystemExit("serving errors: %r" % r["errors"][:3])
+    s0 = [q for q in r["requests"] if q.session == 0]
+    finals.add((s0[-1].result["count"], s0[-1].result["set_hash"]))
+    out["two_sessions"] = {"streams": "seed 2 and seed 4, 200 batches each", "slots": 2,
+                           "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "mean_ms": r["mean_ms"],
+                           "batches_per_s": r["throughput_batches_per_s"],
+                           "max_overlap_sessions": r["max_overlap_sessions"]}
+    log("serving two sessions: p50 %.2f p99 %.2f ms, %.1f batches/s" % (r["p50_ms"], r["p99_ms"],
+                                                                          r["throughput_batches_per_s"]))
     if len(finals) != 1:
         raise SystemExit("serving runs disagree: %r" % finals)
     cnt, h = finals.pop()
