@@ -39,3 +39,18 @@ def test_tuned_knobs_are_accepted_by_every_entry_point():
         kw = set(tuner.launch_kwargs(p))
         assert kw <= static, kw - static
         assert kw <= state, kw - state
+
+
+def test_bench_traffic_is_tied_to_the_kernel_sources(monkeypatch):
+    # the committed counter summary is reported only for the kernels it was
+    # measured on
+    import json
+    import os
+    import bench
+    path = os.path.join(bench.ROOT, "profiles", "traffic_cl1m_communities_degree.json")
+    with open(path) as f:
+        rec = json.load(f)
+    if rec["kernel_sources"] == bench.kernel_sources_digest():
+        assert bench.measured_traffic(None) == rec["bytes_per_call"]
+    monkeypatch.setattr(bench, "kernel_sources_digest", lambda: "0" * 16)
+    assert bench.measured_traffic(None) is None
