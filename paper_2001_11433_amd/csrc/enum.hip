@@ -360,7 +360,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
                             uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since, const WideCtx* wide,
                             Diag& dg) {
   const int lane = lane_id();
-  uint32_t d = 0;
+  uint32_t d = 0;       // frames on the stack
+  uint32_t kl = kbase;  // |K| of the current node (a last child reuses its parent's frame slot)
   const uint64_t tn0 = acc.tn, t0 = now();
   for (;;) {
     bool pop = false;
@@ -368,7 +369,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       expand = false;
       ++acc.tn;
       if (P == 0) {
-        if ((Xp | Xx) == 0) emit(a, acc, zsum, kbase + d, L.kG);
+        if ((Xp | Xx) == 0) emit(a, acc, zsum, kl, L.kG);
         pop = true;
       } else {
         const uint64_t mP = P | Xp;
@@ -404,10 +405,10 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         ++acc.tn;
         if (((Xp & rq) | (Xx & rqx)) == 0) {
           if (a.cl_vert) {
-            if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
+            if (lane == 0) L.kG[kl] = readlane32(c.gP, q);
             __syncthreads();  // the K list is read by every lane
           }
-          emit(a, acc, zsum + readlane64(c.zP, q), kbase + d + 1, L.kG);
+          emit(a, acc, zsum + readlane64(c.zP, q), kl + 1, L.kG);
         }
         continue;
       }
@@ -430,17 +431,18 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
           ++acc.tn;
           if (a.cl_vert) {
             if (lane == 0) {
-              L.kG[kbase + d] = readlane32(c.gP, q);
-              L.kG[kbase + d + 1] = readlane32(c.gP, w);
+              L.kG[kl] = readlane32(c.gP, q);
+              L.kG[kl + 1] = readlane32(c.gP, w);
             }
             __syncthreads();  // the K list is read by every lane
           }
-          emit(a, acc, zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kbase + d + 2, L.kG);
+          emit(a, acc, zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2, L.kG);
         }
         continue;
       }
-      {
-        // one lane stores the (uniform) frame words
+      if (ext) {
+        // other children follow: save this node (one lane stores the uniform
+        // frame words).  The last child takes the node's place instead.
         if (lane == 0) {
           uint64_t* f = &L.cstk[d * kCF];
           f[0] = P;
@@ -449,15 +451,17 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
           f[3] = ext;
           f[4] = zsum;
           f[5] = EXCL ? F : 0;
+          f[6] = kl;
         }
+        ++d;
       }
-      if (lane == 0) L.kG[kbase + d] = readlane32(c.gP, q);
+      if (lane == 0) L.kG[kl] = readlane32(c.gP, q);
+      ++kl;
       P = cP;
       Xp &= rq;
       Xx &= rqx;
       if (EXCL) F |= readlane64(c.rowEx, q);
       zsum += readlane64(c.zP, q);
-      ++d;
       expand = true;
 
       if (can_donate && ++since >= 4 * a.donate_interval) {
@@ -474,7 +478,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
             e = L.cstk[i * kCF + 3];
             if (e) break;
           }
-          const uint32_t klen = kbase + i;
+          const uint32_t klen = (uint32_t)L.cstk[i * kCF + 6];
           if (i < d && kCR_K + (klen + 1) / 2 <= kBlockWords) {
             const uint32_t keep = (uint32_t)__popcll(e) / 2;
             uint64_t don = e;
@@ -523,13 +527,14 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       return;
     }
     --d;
-    const uint64_t v = lane < 6 ? L.cstk[d * kCF + lane] : 0;
+    const uint64_t v = lane < 7 ? L.cstk[d * kCF + lane] : 0;
     P = readlane64(v, 0);
     Xp = readlane64(v, 1);
     Xx = readlane64(v, 2);
     ext = readlane64(v, 3);
     zsum = readlane64(v, 4);
-    F = readlane64(v, 5);
+    if (EXCL) F = readlane64(v, 5);
+    kl = (uint32_t)readlane64(v, 6);
   }
 }
 
