@@ -377,8 +377,12 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         const uint32_t k2 = ((Xx >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowXP) << 16) | c.keyX) : 0u;
         const uint32_t mx = wave_max_u32(k1 > k2 ? k1 : k2);
         const uint32_t row = mx & 0xFFu;
-        const uint64_t rpP = readlane64(c.rowPP, row & 63), rpX = readlane64(c.rowXP, row & 63);
-        ext = P & ~(row < 64 ? rpP : rpX);
+        uint64_t prow;  // the pivot's row over the cand columns (a cand or a fini row)
+        if (row < 64)
+          prow = readlane64(c.rowPP, row);
+        else
+          prow = readlane64(c.rowXP, row & 63);
+        ext = P & ~prow;
         const uint64_t sm = (uint64_t)__popcll(P) + __popcll(Xp) + __popcll(Xx);
         acc.ssum += sm;
         acc.esum += (uint64_t)__popcll(ext);
