@@ -113,7 +113,9 @@ typedef struct {
   uint64_t subproblems; /* subproblems that needed a search (|cand| > 0) */
   uint64_t max_cand;    /* largest |cand| of a subproblem */
   uint64_t alg_ops;     /* algorithmic 32-bit integer operations of the search: per node
-                           3*s*ceil(|cand|/32) + 2*s + 2*|ext|*ceil(s/32), s = |cand u fini| */
+                           3*s*w + 2*|ext|*w + 2*s, s = |cand u fini| at the node, w =
+                           ceil((|cand| + |relevant fini|)/32) of its subproblem's root (the
+                           32-bit words of one bit row); leaves count none */
   double rank_ms, build_ms, enum_ms; /* device time of ranking, subproblem build + queue, enumeration */
   uint32_t retries;     /* enumeration restarts after a DFS stack overflow */
   uint32_t pad;
