@@ -24,7 +24,8 @@
 // Pins: the clique sets, counts and hashes are pinned by brute force, closed
 // forms and the paper's worked examples (see the tests).  Search-node counts
 // depend on the tie-break reading above; closed forms pin them only for
-// complete graphs (2n - 1 under degree rank) and edgeless graphs (n); beyond
+// complete graphs (2n - 1 under degree rank), stars (2k + 1 under degree and
+// degeneracy rank) and edgeless graphs (n); beyond
 // those they are parity unpinned (checked oracle against GPU only).
 //
 // Build: g++ -O2 -std=c++17 -shared -fPIC -pthread mce_oracle.cpp -o libmce_oracle.so

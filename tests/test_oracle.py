@@ -158,6 +158,21 @@ def test_complete_graph_one_clique_and_node_count(n):
     assert r.nodes == 2 * n - 1
 
 
+@pytest.mark.parametrize("k", [2, 3, 17, 200])
+@pytest.mark.parametrize("rank", ["degree", "degeneracy"])
+def test_star_node_count(k, rank):
+    # star with centre 0 and k leaves.  Degree rank: each leaf owns its edge
+    # (root with cand = {centre}, then the leaf K = {leaf, centre}: 2 nodes)
+    # and the centre's cand is empty (1 dead-end node).  Degeneracy rank (all
+    # core numbers 1, ties by id): the centre owns everything (root + k leaf
+    # children, the pivot is a leaf with t = 0 so ext = all leaves) and each
+    # leaf has an empty cand (1 node).  Either way 2k + 1 nodes, k cliques.
+    g = gg.star(k + 1)
+    r = O.mce_parmce(g, rank)
+    assert r.count == k
+    assert r.nodes == 2 * k + 1
+
+
 @pytest.mark.parametrize("n", [1, 5, 64])
 def test_edgeless_graph_singletons(n):
     g = gg.edgeless(n)
