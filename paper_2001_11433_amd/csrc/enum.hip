@@ -538,7 +538,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
     ext = readlane64(v, 3);
     zsum = readlane64(v, 4);
     if (EXCL) F = readlane64(v, 5);
-    kl = (uint32_t)readlane64(v, 6);
+    kl = readlane32((uint32_t)v, 6);
   }
 }
 
