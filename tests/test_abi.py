@@ -62,3 +62,27 @@ def test_oracle_and_library_share_no_code():
         if path.endswith((".py", ".cpp")):
             txt = open(path).read()
             assert "paper_2001_11433_amd" not in txt, path
+
+
+def test_header_compiles_as_c99(tmp_path):
+    # the boundary is a C ABI: a plain C caller must be able to use the header
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "mce.h"\n'
+        "int use(void) {\n"
+        "  mce_csr g = {0};\n"
+        "  mce_opts o = {0};\n"
+        "  mce_result r;\n"
+        "  imce_result b;\n"
+        "  (void)b;\n"
+        "  o.sched = MCE_SCHED_DEGREE;\n"
+        "  return mce_static(&g, MCE_RANK_DEGENERACY, &o, &r, 0, 0) == MCE_OK ? 0 : 1;\n"
+        "}\n")
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I", inc, str(src)],
+                   check=True)
