@@ -171,6 +171,77 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 5, epoc
     return out
 
 
+def ownership_and_imbalance(m, dg, ref, launch, base_rank: str):
+    """The same graph under every ownership rank (Section 4.2): the clique set
+    (count and hash) must not change, the node count and the split between
+    ranking time and enumeration time do.  Then the imbalance of the base
+    rank's subproblems (the analog of the paper's Figure 2): the smallest share
+    of subproblems that holds 90 % of the search nodes and of the cliques."""
+    out = {"ranks": {}}
+    for rank in ("degree", "degeneracy", "triangle", "ttt_root"):
+        per_vertex = rank == base_rank
+        try:
+            r = m.mce_static(dg, rank=rank, per_vertex=per_vertex, **launch)
+        except m.MceError as e:  # e.g. a subproblem above the supported cand size
+            out["ranks"][rank] = {"error": str(e)}
+            log("ownership %s: %s" % (rank, e))
+            continue
+        if (r["count"], r["set_hash"]) != ref:
+            raise SystemExit("ownership rank %s changed the clique set: %r" % (rank, (r["count"], r["set_hash"])))
+        out["ranks"][rank] = {"rank_ms": r["rank_ms"], "build_ms": r["build_ms"], "enum_ms": r["enum_ms"],
+                              "search_nodes": r["nodes_total"], "max_cand": r["max_cand"]}
+        log("ownership %s: rank %.1f ms, build %.1f ms, enum %.1f ms, %d nodes" % (
+            rank, r["rank_ms"], r["build_ms"], r["enum_ms"], r["nodes_total"]))
+        if per_vertex:
+            def share(x):
+                x = np.sort(x.astype(np.float64))[::-1]
+                tot = x.sum()
+                if tot == 0:
+                    return 0.0
+                k = int(np.searchsorted(np.cumsum(x), 0.9 * tot)) + 1
+                return k / float(x.size)
+            nodes = r["nodes_v"].cpu().numpy().view(np.uint64)
+            count = r["count_v"].cpu().numpy().view(np.uint64)
+            out["imbalance"] = {
+                "rank": rank, "subproblems": int(nodes.size),
+                "share_of_subproblems_for_90pct_nodes": share(nodes),
+                "share_of_subproblems_for_90pct_cliques": share(count),
+                "largest_subproblem_share_of_nodes": float(nodes.max()) / float(nodes.sum()),
+            }
+    return out
+
+
+def decompositions(m, repeats: int = 3):
+    """ParMCE (per-vertex ownership, Algorithm 4) against ParTTT (Algorithm 3
+    applied to the whole-graph root) on the same kernels, on the graphs whose
+    root pivot fits the supported subproblem width."""
+    import graphgen as gg
+    from paper_2001_11433_amd import tuner
+    out = {}
+    for name, g, fam in (("rmat14", gg.rmat(14, 16, 0.57, 0.19, 0.19, seed=0), "rmat14"),
+                         ("cl500k", gg.chung_lu(500_000, 2.2, 16, seed=0), "cl500k")):
+        dg = m.DeviceGraph.from_graph(g)
+        row, ref = {}, None
+        for rank in ("degree", "degeneracy", "ttt_root"):
+            kw = tuner.launch_kwargs(tuner.lookup(g, rank if rank != "ttt_root" else "degree", family=fam))
+            ts = []
+            for _ in range(repeats):
+                r = m.mce_static(dg, rank=rank, **kw)
+                ts.append(r["rank_ms"] + r["build_ms"] + r["enum_ms"])
+            key = (r["count"], r["set_hash"])
+            ref = ref or key
+            if key != ref:
+                raise SystemExit("decomposition %s changed the clique set on %s" % (rank, name))
+            row[rank] = {"device_ms": _median(ts), "search_nodes": r["nodes_total"], "max_cand": r["max_cand"]}
+        row["maximal_cliques"] = ref[0]
+        row["parmce_over_parttt"] = row["ttt_root"]["device_ms"] / min(row["degree"]["device_ms"],
+                                                                       row["degeneracy"]["device_ms"])
+        log("decompositions %s: %s" % (name, {k: round(v["device_ms"], 1) for k, v in row.items()
+                                              if isinstance(v, dict)}))
+        out[name] = row
+    return out
+
+
 def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
     """Online IMCE: one session, 200 edge-addition batches; closed loop
     (back to back) repeated, then open-loop Poisson arrivals at fractions of
@@ -286,6 +357,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-ownership", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--learned-scale", type=int, default=14)
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
@@ -359,6 +431,10 @@ def main():
                      "kernel": "k_enum + k_compact (the enumeration: both launches)",
                      "ops_per_launch": r0["alg_ops"]},
     }
+    if not args.no_ownership:
+        log("ownership ranks and imbalance ...")
+        out["ownership"] = ownership_and_imbalance(m, dg, (r0["count"], r0["set_hash"]), launch, rank)
+        out["decompositions"] = decompositions(m)
     if not args.no_learned:
         log("learned scheduling ...")
         out["learned_sched"] = learned_sched(m, args.learned_scale, range(1, 11), (11, 12))

@@ -65,7 +65,20 @@ typedef struct {
  * rank(v) = (metric(v), id(v)) compared lexicographically, metric = degree,
  * core number (degeneracy), or number of triangles through v.  Subproblem v
  * reports exactly the cliques in which v has the lowest rank. */
-typedef enum { MCE_RANK_DEGREE = 0, MCE_RANK_DEGENERACY = 1, MCE_RANK_TRIANGLE = 2 } mce_rank;
+typedef enum {
+  MCE_RANK_DEGREE = 0,
+  MCE_RANK_DEGENERACY = 1,
+  MCE_RANK_TRIANGLE = 2,
+  /* No per-vertex ownership: Algorithm 3 (ParTTT) applied to the root of
+   * Algorithm 1 on the whole graph (K = {}, cand = V, fini = {}).  The root's
+   * pivot u is a vertex of largest degree (smallest id on ties) and every
+   * q in ext = V \ Gamma(u), in ascending id, becomes a task with
+   * cand = Gamma(q) minus the earlier ext vertices and fini = Gamma(q) n the
+   * earlier ext vertices (Algorithm 3's child formula).  The root counts as
+   * one search node; per-vertex outputs describe the root's children.
+   * mce_rank_metric writes 0 for the children and 2^63 for u's neighbours. */
+  MCE_RANK_TTT_ROOT = 3
+} mce_rank;
 
 /* Order in which subproblems enter the work queue (largest key first).  It
  * changes only the schedule, never the cliques, hashes or node counts. */

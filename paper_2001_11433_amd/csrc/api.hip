@@ -174,6 +174,10 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
     case MCE_RANK_TRIANGLE:
       MCE_TRY_HIP(launch_triangles(n, rp, col, metric, s));
       return MCE_OK;
+    case MCE_RANK_TTT_ROOT:
+      MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
+      MCE_TRY_HIP(launch_root_metric(n, rp, col, metric, ws.corectl.as<uint64_t>(), s));
+      return MCE_OK;
   }
   set_error("unknown rank %d", (int)rank);
   return MCE_EINVAL;
@@ -328,7 +332,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     set_error("n must be below 2^32 - 1");
     return MCE_ENOTSUP;
   }
-  if (rank != MCE_RANK_DEGREE && rank != MCE_RANK_DEGENERACY && rank != MCE_RANK_TRIANGLE) {
+  if (rank != MCE_RANK_DEGREE && rank != MCE_RANK_DEGENERACY && rank != MCE_RANK_TRIANGLE &&
+      rank != MCE_RANK_TTT_ROOT) {
     set_error("unknown rank %d", (int)rank);
     return MCE_EINVAL;
   }
@@ -525,7 +530,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   MCE_TRY_HIP(hipStreamSynchronize(s));
   out->count = stats[3] + ctl[CTL_COUNT];
   out->set_hash = stats[4] + ctl[CTL_HASH];
-  out->nodes_total = stats[5] + ctl[CTL_NODES];
+  // the whole-graph root itself is one more search node
+  out->nodes_total = stats[5] + ctl[CTL_NODES] + (rank == MCE_RANK_TTT_ROOT ? 1 : 0);
   out->donated = ctl[CTL_DONATED];
   out->alg_ops = ctl[CTL_OPS];
   for (int k = 0; k < 8; ++k) out->diag[k] = ctl[CTL_DIAG + k];

@@ -35,10 +35,15 @@ __global__ void k_sizes(uint64_t n, const uint64_t* __restrict__ rp, const uint3
   if (v < n) {
     uint64_t b = rp[v], e = rp[v + 1];
     uint32_t p = 0;
-    for (uint64_t i = b; i < e; ++i) p += rank_gt(metric, col[i], (uint32_t)v) ? 1u : 0u;
+    // bit 63 of the metric: v owns no subproblem (MCE_RANK_TTT_ROOT)
+    const bool owner = !(metric[v] >> 63);
+    if (owner)
+      for (uint64_t i = b; i < e; ++i) p += rank_gt(metric, col[i], (uint32_t)v) ? 1u : 0u;
     P[v] = p;
     uint64_t nv = 0, cv = 0, hv = 0;
-    if (p == 0) {
+    if (!owner) {
+      // no subproblem, no node
+    } else if (p == 0) {
       // cand is empty: a single search node; {v} is maximal iff fini is empty
       nv = 1;
       if (e == b) {

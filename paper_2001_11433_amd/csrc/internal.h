@@ -184,6 +184,11 @@ uint32_t enum_grid(const mce_opts& opts);
 // rank.hip
 hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s);
 hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipStream_t s);
+// MCE_RANK_TTT_ROOT: metric 0 for the children of the whole-graph root, bit 63
+// for the root pivot's neighbours (no subproblem of their own); `best` is one
+// u64 of scratch.
+hipError_t launch_root_metric(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* metric, uint64_t* best,
+                              hipStream_t s);
 int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg_scratch,
                      uint64_t* ctl_scratch, hipStream_t s);
 hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s);

@@ -140,6 +140,34 @@ inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs 
 
 }  // namespace
 
+// --- whole-graph TTT root (Algorithm 3 at the top level) -------------------
+
+// The root's pivot u maximises |V n Gamma(u)| = d(u), smallest id on ties:
+// the maximum of (d << 32) | (2^32 - 1 - id).
+__global__ void k_root_pivot(uint64_t n, const uint64_t* __restrict__ rp, uint64_t* best) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t key = 0;
+  if (v < n) key = ((rp[v + 1] - rp[v]) << 32) | (0xFFFFFFFFULL - v);
+  key = wave_max_u64(key);
+  if (lane_id() == 0 && key) atomicMax((unsigned long long*)best, (unsigned long long)key);
+}
+
+// metric = 0 for the root's children (ext = V \ Gamma(u), ranked by id),
+// bit 63 for the pivot's neighbours, which own no subproblem and rank above
+// every child (they stay in every child's cand).
+__global__ void k_root_metric_clear(uint64_t n, uint64_t* metric) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v < n) metric[v] = 0;
+}
+
+__global__ void k_root_metric_mark(const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                                   const uint64_t* __restrict__ best, uint64_t* metric) {
+  const uint32_t u = 0xFFFFFFFFu - (uint32_t)(*best & 0xFFFFFFFFULL);
+  for (uint64_t j = rp[u] + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < rp[u + 1];
+       j += (uint64_t)gridDim.x * blockDim.x)
+    metric[col[j]] = 1ULL << 63;
+}
+
 hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, uint32_t* bad, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, bad);
@@ -149,6 +177,17 @@ hipError_t launch_validate(uint64_t n, const uint64_t* rp, const uint32_t* col, 
 hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_degree, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, metric);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_metric(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* metric, uint64_t* best,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(best, 0, sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_root_pivot, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, best);
+  hipLaunchKernelGGL(k_root_metric_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, metric);
+  hipLaunchKernelGGL(k_root_metric_mark, dim3(64), dim3(256), 0, s, rp, col, best, metric);
   return hipGetLastError();
 }
 

@@ -162,6 +162,44 @@ def test_repeated_runs_with_heavy_block_recycling(m):
         assert got["donated"] > 0
 
 
+TTT_ROOT_GRAPHS = [
+    ("K1", lambda: gg.complete(1)),
+    ("K40", lambda: gg.complete(40)),
+    ("edgeless7", lambda: gg.edgeless(7)),
+    ("C9", lambda: gg.cycle(9)),
+    ("star50", lambda: gg.star(50)),
+    ("moon_moser24", lambda: gg.moon_moser(24)),
+    ("multipartite", lambda: gg.complete_multipartite([4, 1, 3, 5, 2])),
+    ("er300", lambda: gg.er(300, 0.08, seed=3)),
+    ("rmat10", lambda: gg.rmat(10, seed=2)),
+    ("rmat11", lambda: gg.rmat(11, seed=4)),
+    ("communities", lambda: gg.plant_communities(gg.chung_lu(3000, 2.1, 10, seed=0), count=6, smin=30, smax=45,
+                                                 p=0.9, seed=1)),
+]
+
+
+@pytest.mark.parametrize("name,make", TTT_ROOT_GRAPHS, ids=[x[0] for x in TTT_ROOT_GRAPHS])
+def test_whole_graph_ttt_root_split(m, name, make):
+    # Algorithm 3 on the root of Algorithm 1: same clique set as Algorithm 1
+    # from the root, and the same recursion tree (node count, root included)
+    g = make()
+    got = m.mce_static(g, rank="ttt_root", cliques=g.n <= 400)
+    want = O.mce_root(g, cliques=g.n <= 400)
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == tuple(want[:3])
+    if g.n <= 400:
+        assert got["cliques"] == want[3]
+
+
+def test_ttt_root_metric_marks_the_pivot_neighbours(m):
+    g = gg.rmat(10, seed=8)
+    deg = np.diff(np.asarray(g.row_ptr, dtype=np.int64))
+    u = int(np.flatnonzero(deg == deg.max())[0])
+    want = np.zeros(g.n, dtype=np.uint64)
+    want[g.neighbors(u)] = np.uint64(1) << np.uint64(63)
+    got = m.mce_rank_metric(g, "ttt_root").cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, want)
+
+
 def test_stack_overflow_retries(m):
     # K_300: 5-word bitsets, too deep for the LDS stack; 4 global frames overflow
     g = gg.complete(300)
