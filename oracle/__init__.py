@@ -25,7 +25,8 @@ _LIB = os.path.join(_HERE, "libmce_oracle.so")
 RANK_DEGREE = 0
 RANK_DEGENERACY = 1
 RANK_TRIANGLE = 2
-RANKS = {"degree": RANK_DEGREE, "degeneracy": RANK_DEGENERACY, "triangle": RANK_TRIANGLE}
+RANK_PEEL = 3
+RANKS = {"degree": RANK_DEGREE, "degeneracy": RANK_DEGENERACY, "triangle": RANK_TRIANGLE, "peel": RANK_PEEL}
 
 
 class _Result(ctypes.Structure):

@@ -26,7 +26,10 @@
 // depend on the tie-break reading above; closed forms pin them only for
 // complete graphs (2n - 1 under degree rank), stars (2k + 1 under degree and
 // degeneracy rank) and edgeless graphs (n); beyond
-// those they are parity unpinned (checked oracle against GPU only).
+// those they are parity unpinned (checked oracle against GPU only).  The
+// peel-round metric is pinned by closed forms on paths, cycles and stars, by
+// its first round (exactly the vertices of minimum degree), by invariance under
+// relabelling, and by the bound of later neighbours by the core number.
 //
 // Build: g++ -O2 -std=c++17 -shared -fPIC -pthread mce_oracle.cpp -o libmce_oracle.so
 
@@ -219,7 +222,7 @@ void ttt(const Graph& G, std::vector<uint32_t>& K, VSet cand, VSet fini, Sink& o
 }
 
 // Vertex metric behind the rank functions of Section 4.2.
-enum { RANK_DEGREE = 0, RANK_DEGENERACY = 1, RANK_TRIANGLE = 2 };
+enum { RANK_DEGREE = 0, RANK_DEGENERACY = 1, RANK_TRIANGLE = 2, RANK_PEEL = 3 };
 
 // Core numbers by Batagelj-Zaversnik bucket peeling: repeatedly remove a vertex
 // of minimum remaining degree; its core number is the running maximum of the
@@ -267,9 +270,45 @@ std::vector<uint64_t> triangle_counts(const Adj& A) {
   return t;
 }
 
+// Peel order: the degeneracy ordering of Eppstein, Loeffler and Strash taken
+// in synchronous rounds.  Level k starts at 0.  A round removes, all at once,
+// every remaining vertex whose degree in the remaining graph is at most k, and
+// the vertex's metric is the index of that round.  A round that would remove
+// nothing instead raises k to the smallest remaining degree and is not counted.
+// A vertex leaving at level k has at most k neighbours that leave in the same
+// round or later, so with rank (round, id) its candidate set is no larger than
+// its core number.
+std::vector<uint64_t> peel_rounds(const Adj& A) {
+  uint64_t n = A.rows.size();
+  std::vector<uint64_t> deg(n), round(n, ~0ULL);
+  for (uint64_t v = 0; v < n; ++v) deg[v] = A.deg(v);
+  uint64_t k = 0, r = 0, left = n;
+  while (left > 0) {
+    std::vector<uint32_t> out;
+    uint64_t mind = ~0ULL;
+    for (uint64_t v = 0; v < n; ++v) {
+      if (round[v] != ~0ULL) continue;
+      if (deg[v] <= k) out.push_back((uint32_t)v);
+      else mind = std::min(mind, deg[v]);
+    }
+    if (out.empty()) {
+      k = mind;
+      continue;
+    }
+    for (uint32_t v : out) round[v] = r;
+    for (uint32_t v : out)
+      for (uint32_t w : A.rows[v])
+        if (round[w] == ~0ULL) deg[w] -= 1;
+    left -= out.size();
+    ++r;
+  }
+  return round;
+}
+
 std::vector<uint64_t> metric_of(const Adj& A, int kind) {
   uint64_t n = A.rows.size();
   if (kind == RANK_DEGENERACY) return core_numbers(A);
+  if (kind == RANK_PEEL) return peel_rounds(A);
   if (kind == RANK_TRIANGLE) return triangle_counts(A);
   std::vector<uint64_t> d(n);
   for (uint64_t v = 0; v < n; ++v) d[v] = A.deg(v);

@@ -20,7 +20,7 @@ import graphgen as gg
 import oracle as O
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-RANKS = ("degree", "degeneracy", "triangle")
+RANKS = ("degree", "degeneracy", "triangle", "peel")
 
 
 # --------------------------------------------------------------------------
@@ -283,6 +283,42 @@ def test_rank_metrics_match_definitions():
         A[v, u] = 1
         tri = np.diag(A @ A @ A) // 2
         assert np.array_equal(O.rank_metric(g, "triangle").astype(np.int64), tri)
+
+
+# Peel rounds: closed forms on paths, cycles and stars.
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 40])
+def test_peel_rounds_on_paths_cycles_stars(n):
+    path = gg.path(n)
+    assert list(O.rank_metric(path, "peel")) == [min(i, n - 1 - i) for i in range(n)]
+    if n >= 3:
+        cyc = gg.cycle(n)
+        assert list(O.rank_metric(cyc, "peel")) == [0] * n
+    if n >= 3:
+        star = gg.star(n)
+        assert list(O.rank_metric(star, "peel")) == [1] + [0] * (n - 1)
+
+
+def test_peel_rounds_invariants():
+    rng = np.random.default_rng(5)
+    for seed in range(12):
+        n = int(rng.integers(5, 70))
+        g = gg.er(n, float(rng.choice([0.05, 0.15, 0.4])), seed=seed)
+        r = O.rank_metric(g, "peel").astype(np.int64)
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        # the first round takes exactly the vertices of minimum degree
+        assert set(np.flatnonzero(r == 0)) == set(np.flatnonzero(deg == deg.min()))
+        # rounds do not depend on vertex ids: relabel and compare
+        perm = rng.permutation(n)
+        h = gg.relabel(g, perm)
+        rh = O.rank_metric(h, "peel").astype(np.int64)
+        assert np.array_equal(rh[perm], r)
+        # Eppstein's bound: neighbours later in (round, id) number at most the
+        # core number
+        core = _k_core_numbers(g)
+        for x in range(n):
+            nb = g.col[g.row_ptr[x]:g.row_ptr[x + 1]]
+            later = sum(1 for w in nb if (r[w], w) > (r[x], x))
+            assert later <= core[x]
 
 
 # --------------------------------------------------------------------------
