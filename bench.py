@@ -178,7 +178,7 @@ def ownership_and_imbalance(m, dg, ref, launch, base_rank: str):
     rank's subproblems (the analog of the paper's Figure 2): the smallest share
     of subproblems that holds 90 % of the search nodes and of the cliques."""
     out = {"ranks": {}}
-    for rank in ("degree", "degeneracy", "triangle", "ttt_root"):
+    for rank in ("degree", "degeneracy", "triangle", "peel", "ttt_root"):
         per_vertex = rank == base_rank
         try:
             r = m.mce_static(dg, rank=rank, per_vertex=per_vertex, **launch)
@@ -222,8 +222,9 @@ def decompositions(m, repeats: int = 3):
                          ("cl500k", gg.chung_lu(500_000, 2.2, 16, seed=0), "cl500k")):
         dg = m.DeviceGraph.from_graph(g)
         row, ref = {}, None
-        for rank in ("degree", "degeneracy", "ttt_root"):
-            kw = tuner.launch_kwargs(tuner.lookup(g, rank if rank != "ttt_root" else "degree", family=fam))
+        for rank in ("degree", "degeneracy", "peel", "ttt_root"):
+            like = {"ttt_root": "degree", "peel": "degeneracy"}.get(rank, rank)
+            kw = tuner.launch_kwargs(tuner.lookup(g, like, family=fam))
             ts = []
             for _ in range(repeats):
                 r = m.mce_static(dg, rank=rank, **kw)
@@ -234,8 +235,8 @@ def decompositions(m, repeats: int = 3):
                 raise SystemExit("decomposition %s changed the clique set on %s" % (rank, name))
             row[rank] = {"device_ms": _median(ts), "search_nodes": r["nodes_total"], "max_cand": r["max_cand"]}
         row["maximal_cliques"] = ref[0]
-        row["parmce_over_parttt"] = row["ttt_root"]["device_ms"] / min(row["degree"]["device_ms"],
-                                                                       row["degeneracy"]["device_ms"])
+        row["parmce_over_parttt"] = row["ttt_root"]["device_ms"] / min(
+            row[k]["device_ms"] for k in ("degree", "degeneracy", "peel"))
         log("decompositions %s: %s" % (name, {k: round(v["device_ms"], 1) for k, v in row.items()
                                               if isinstance(v, dict)}))
         out[name] = row

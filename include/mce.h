@@ -77,7 +77,15 @@ typedef enum {
    * earlier ext vertices (Algorithm 3's child formula).  The root counts as
    * one search node; per-vertex outputs describe the root's children.
    * mce_rank_metric writes 0 for the children and 2^63 for u's neighbours. */
-  MCE_RANK_TTT_ROOT = 3
+  MCE_RANK_TTT_ROOT = 3,
+  /* metric = peel round: the degeneracy ordering (Eppstein, Loeffler and
+   * Strash) taken in synchronous rounds.  Level k starts at 0; a round
+   * removes at once every remaining vertex whose remaining degree is <= k and
+   * gives it the round's index; a round that would remove nobody instead
+   * raises k to the smallest remaining degree and is not counted.  Every
+   * vertex then has at most core(v) neighbours of higher rank, so no cand set
+   * exceeds the degeneracy.  The rounds depend on the graph only. */
+  MCE_RANK_PEEL = 4
 } mce_rank;
 
 /* Order in which subproblems enter the work queue (largest key first).  It

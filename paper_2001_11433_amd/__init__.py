@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmce.so")
 
 MCE_OK, MCE_EINVAL, MCE_ENOMEM, MCE_ENOSPC, MCE_EDEVICE, MCE_ENOTSUP = 0, -1, -2, -3, -4, -5
-RANKS = {"degree": 0, "degeneracy": 1, "triangle": 2, "ttt_root": 3}
+RANKS = {"degree": 0, "degeneracy": 1, "triangle": 2, "ttt_root": 3, "peel": 4}
 SCHEDS = {"degree": 0, "triangle": 1, "cost": 2, "id": 3}
 
 

@@ -174,6 +174,10 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
     case MCE_RANK_TRIANGLE:
       MCE_TRY_HIP(launch_triangles(n, rp, col, metric, s));
       return MCE_OK;
+    case MCE_RANK_PEEL:
+      MCE_TRY(ws.coredeg.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
+      MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
+      return run_peel_rounds(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corectl.as<uint64_t>(), s);
     case MCE_RANK_TTT_ROOT:
       MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
       MCE_TRY_HIP(launch_root_metric(n, rp, col, metric, ws.corectl.as<uint64_t>(), s));
@@ -333,7 +337,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     return MCE_ENOTSUP;
   }
   if (rank != MCE_RANK_DEGREE && rank != MCE_RANK_DEGENERACY && rank != MCE_RANK_TRIANGLE &&
-      rank != MCE_RANK_TTT_ROOT) {
+      rank != MCE_RANK_TTT_ROOT && rank != MCE_RANK_PEEL) {
     set_error("unknown rank %d", (int)rank);
     return MCE_EINVAL;
   }

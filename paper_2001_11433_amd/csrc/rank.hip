@@ -85,6 +85,68 @@ __global__ void k_core_advance(uint64_t* ctl) {
   ctl[2] = ~0ULL;
 }
 
+// --- peel rounds: the degeneracy ordering taken in synchronous rounds -------
+// Same levels as the core peeling above, but a round is split in two kernels:
+// k_peel_mark decides who leaves from the degrees at the start of the round,
+// and only then k_peel_drop takes the leaving vertices out of their
+// neighbours' degrees.  The round a vertex leaves in is therefore fixed by the
+// graph alone, not by the order in which waves run.
+// ctl: [0] level k, [1] removed in this round, [2] min remaining degree seen,
+//      [3] vertices remaining, [4] round index.
+__global__ void k_peel_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_t* deg, uint64_t* round,
+                            uint64_t* ctl) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v < n) {
+    deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
+    round[v] = kAlive;
+  }
+  if (v == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = ~0ULL;
+    ctl[3] = n;
+    ctl[4] = 0;
+  }
+}
+
+__global__ void k_peel_mark(uint64_t n, const uint32_t* __restrict__ deg, uint64_t* round, uint64_t* ctl) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t k = ctl[0];
+  bool removed = false;
+  if (v < n && round[v] == kAlive) {
+    uint32_t d = deg[v];
+    if (d <= k) {
+      round[v] = ctl[4];
+      removed = true;
+    } else {
+      atomicMin((unsigned long long*)&ctl[2], (unsigned long long)d);
+    }
+  }
+  uint64_t cnt = __popcll(ballot(removed));
+  if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)cnt);
+}
+
+__global__ void k_peel_drop(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                            uint32_t* deg, const uint64_t* __restrict__ round, const uint64_t* __restrict__ ctl) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n || ctl[1] == 0 || round[v] != ctl[4]) return;
+  for (uint64_t i = rp[v]; i < rp[v + 1]; ++i) {
+    uint32_t w = col[i];
+    if (round[w] == kAlive) atomicSub(&deg[w], 1u);
+  }
+}
+
+// A round that removed nobody raises the level to the smallest remaining
+// degree and keeps its index; otherwise the index advances.
+__global__ void k_peel_advance(uint64_t* ctl) {
+  uint64_t removed = ctl[1];
+  ctl[3] -= removed;
+  if (removed) ctl[4] += 1;
+  else if (ctl[3] > 0) ctl[0] = ctl[2];
+  ctl[1] = 0;
+  ctl[2] = ~0ULL;
+}
+
 // --- triangles -------------------------------------------------------------
 // One wave per vertex v.  Each triangle is found once, from its lowest vertex
 // in the order (degree, id): v < u < w; all three endpoints are credited.
@@ -204,6 +266,31 @@ int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64
     for (uint32_t r = 0; r < group; ++r) {
       hipLaunchKernelGGL(k_core_round, dim3(g), dim3(256), 0, s, n, rp, col, deg, core, ctl);
       hipLaunchKernelGGL(k_core_advance, dim3(1), dim3(1), 0, s, ctl);
+    }
+    MCE_TRY_HIP(hipGetLastError());
+    uint64_t remaining = 0;
+    MCE_TRY_HIP(hipMemcpyAsync(&remaining, ctl + 3, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    MCE_TRY_HIP(hipStreamSynchronize(s));
+    if (remaining == 0) break;
+    if (group < 256) group *= 2;
+  }
+  return MCE_OK;
+}
+
+int run_peel_rounds(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* round, uint32_t* deg,
+                    uint64_t* ctl, hipStream_t s) {
+  if (n == 0) return MCE_OK;
+  const uint32_t g = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_peel_init, dim3(g), dim3(256), 0, s, n, rp, deg, round, ctl);
+  MCE_TRY_HIP(hipGetLastError());
+  // As for the core numbers: rounds go out in growing groups, and rounds after
+  // the last vertex left change nothing.
+  uint32_t group = 16;
+  for (;;) {
+    for (uint32_t r = 0; r < group; ++r) {
+      hipLaunchKernelGGL(k_peel_mark, dim3(g), dim3(256), 0, s, n, deg, round, ctl);
+      hipLaunchKernelGGL(k_peel_drop, dim3(g), dim3(256), 0, s, n, rp, col, deg, round, ctl);
+      hipLaunchKernelGGL(k_peel_advance, dim3(1), dim3(1), 0, s, ctl);
     }
     MCE_TRY_HIP(hipGetLastError());
     uint64_t remaining = 0;

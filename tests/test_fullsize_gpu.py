@@ -58,7 +58,7 @@ def test_cl1m_communities_sampled_subproblems(m):
     assert np.array_equal(hsh[sample], want.hash_v)
 
 
-@pytest.mark.parametrize("rank", ["degree", "degeneracy", "triangle"])
+@pytest.mark.parametrize("rank", ["degree", "degeneracy", "triangle", "peel"])
 def test_rmat18_rank_metrics(m, rank):
     g = gg.rmat(18, 16, 0.57, 0.19, 0.19, seed=0)
     got = m.mce_rank_metric(g, rank).cpu().numpy().astype(np.uint64)

@@ -13,7 +13,7 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-RANKS = ("degree", "degeneracy", "triangle")
+RANKS = ("degree", "degeneracy", "triangle", "peel")
 
 
 @pytest.fixture(scope="module")
@@ -70,7 +70,7 @@ def test_random_small_graphs_full_sets(m):
         n = int(rng.integers(1, 40))
         p = float(rng.choice([0.05, 0.2, 0.5, 0.8, rng.random()]))
         g = gg.er(n, p, seed=1000 + t)
-        _check(m, g, RANKS[t % 3], cliques=True)
+        _check(m, g, RANKS[t % len(RANKS)], cliques=True)
 
 
 def test_empty_graph(m):
@@ -253,7 +253,7 @@ def test_host_csr_input_path(m):
 
 @pytest.mark.parametrize("rank", RANKS)
 def test_rank_metric_kernels(m, rank):
-    for g in (gg.rmat(12, seed=3), gg.er(500, 0.02, seed=1), gg.edgeless(5)):
+    for g in (gg.rmat(12, seed=3), gg.er(500, 0.02, seed=1), gg.edgeless(5), gg.path(3001), gg.cycle(7)):
         got = _u64(m.mce_rank_metric(g, rank))
         assert np.array_equal(got, O.rank_metric(g, rank))
 
