@@ -212,33 +212,43 @@ def ownership_and_imbalance(m, dg, ref, launch, base_rank: str):
 
 
 def decompositions(m, repeats: int = 3):
-    """ParMCE (per-vertex ownership, Algorithm 4) against ParTTT (Algorithm 3
-    applied to the whole-graph root) on the same kernels, on the graphs whose
-    root pivot fits the supported subproblem width."""
+    """Every ownership rank (Section 4.2, plus the peel order) and ParTTT
+    (Algorithm 3 applied to the whole-graph root) on the same kernels, on the
+    2000-vertex ER graph, R-MAT scale 14 and the 500k Chung-Lu graph:
+    rank + build + search device time, median of `repeats`.  ParTTT runs where
+    the root pivot's non-neighbours fit the supported subproblem width."""
     import graphgen as gg
     from paper_2001_11433_amd import tuner
     out = {}
-    for name, g, fam in (("rmat14", gg.rmat(14, 16, 0.57, 0.19, 0.19, seed=0), "rmat14"),
-                         ("cl500k", gg.chung_lu(500_000, 2.2, 16, seed=0), "cl500k")):
+    for name, make, fam in (("er2000", lambda: gg.er(2000, 0.01, seed=0), None),
+                            ("rmat14", lambda: gg.rmat(14, 16, 0.57, 0.19, 0.19, seed=0), "rmat14"),
+                            ("cl500k", lambda: gg.chung_lu(500_000, 2.2, 16, seed=0), "cl500k")):
+        g = make()
         dg = m.DeviceGraph.from_graph(g)
         row, ref = {}, None
-        for rank in ("degree", "degeneracy", "peel", "ttt_root"):
-            like = {"ttt_root": "degree", "peel": "degeneracy"}.get(rank, rank)
+        for rank in ("degree", "degeneracy", "triangle", "peel", "ttt_root"):
+            like = {"ttt_root": "degree", "peel": "degeneracy", "triangle": "degree"}.get(rank, rank)
             kw = tuner.launch_kwargs(tuner.lookup(g, like, family=fam))
             ts = []
-            for _ in range(repeats):
-                r = m.mce_static(dg, rank=rank, **kw)
-                ts.append(r["rank_ms"] + r["build_ms"] + r["enum_ms"])
+            try:
+                for _ in range(repeats):
+                    r = m.mce_static(dg, rank=rank, **kw)
+                    ts.append(r["rank_ms"] + r["build_ms"] + r["enum_ms"])
+            except m.MceError as e:  # e.g. a root pivot with too many non-neighbours
+                row[rank] = {"error": str(e)}
+                continue
             key = (r["count"], r["set_hash"])
             ref = ref or key
             if key != ref:
                 raise SystemExit("decomposition %s changed the clique set on %s" % (rank, name))
-            row[rank] = {"device_ms": _median(ts), "search_nodes": r["nodes_total"], "max_cand": r["max_cand"]}
+            row[rank] = {"device_ms": _median(ts), "rank_ms": r["rank_ms"], "search_nodes": r["nodes_total"],
+                         "max_cand": r["max_cand"]}
         row["maximal_cliques"] = ref[0]
-        row["parmce_over_parttt"] = row["ttt_root"]["device_ms"] / min(
-            row[k]["device_ms"] for k in ("degree", "degeneracy", "peel"))
+        if "device_ms" in row["ttt_root"]:
+            row["parmce_over_parttt"] = row["ttt_root"]["device_ms"] / min(
+                row[k]["device_ms"] for k in ("degree", "degeneracy", "triangle", "peel") if "device_ms" in row[k])
         log("decompositions %s: %s" % (name, {k: round(v["device_ms"], 1) for k, v in row.items()
-                                              if isinstance(v, dict)}))
+                                              if isinstance(v, dict) and "device_ms" in v}))
         out[name] = row
     return out
 
