@@ -30,7 +30,7 @@ namespace {
 // Device workspace of the static pipeline; grown on demand, reused across
 // calls on the same device, guarded by one mutex per device.
 struct Workspace {
-  DevBuf rp, col, metric, tri, core, coredeg, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
+  DevBuf rp, col, metric, tri, core, coredeg, corelist, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
       gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad, split, split_total;
   EnumWork ew;
   void* scan_tmp = nullptr;
@@ -169,15 +169,19 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
       return MCE_OK;
     case MCE_RANK_DEGENERACY:
       MCE_TRY(ws.coredeg.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
+      MCE_TRY(ws.corelist.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
       MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
-      return run_core_numbers(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corectl.as<uint64_t>(), s);
+      return run_core_numbers(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corelist.as<uint32_t>(),
+                              ws.corectl.as<uint64_t>(), s);
     case MCE_RANK_TRIANGLE:
       MCE_TRY_HIP(launch_triangles(n, rp, col, metric, s));
       return MCE_OK;
     case MCE_RANK_PEEL:
       MCE_TRY(ws.coredeg.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
+      MCE_TRY(ws.corelist.ensure(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
       MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
-      return run_peel_rounds(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corectl.as<uint64_t>(), s);
+      return run_peel_rounds(n, rp, col, metric, ws.coredeg.as<uint32_t>(), ws.corelist.as<uint32_t>(),
+                             ws.corectl.as<uint64_t>(), s);
     case MCE_RANK_TTT_ROOT:
       MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
       MCE_TRY_HIP(launch_root_metric(n, rp, col, metric, ws.corectl.as<uint64_t>(), s));

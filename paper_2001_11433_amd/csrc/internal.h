@@ -189,11 +189,13 @@ hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipSt
 // u64 of scratch.
 hipError_t launch_root_metric(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* metric, uint64_t* best,
                               hipStream_t s);
+// Level-synchronous peeling (see rank.hip): core number or peel round
+// (MCE_RANK_PEEL) of every vertex.  Scratch: deg_scratch and list hold n
+// entries each, ctl 8 words.
 int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg_scratch,
-                     uint64_t* ctl_scratch, hipStream_t s);
-// Peel round of every vertex (MCE_RANK_PEEL); deg_scratch and ctl as above.
+                     uint32_t* list, uint64_t* ctl, hipStream_t s);
 int run_peel_rounds(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* round, uint32_t* deg_scratch,
-                    uint64_t* ctl, hipStream_t s);
+                    uint32_t* list, uint64_t* ctl, hipStream_t s);
 hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s);
 hipError_t launch_features(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* core,
                            const uint64_t* tri, float* feat, hipStream_t s);

@@ -1,5 +1,6 @@
 // Vertex metrics behind the rank functions of Section 4.2 (degree, core
-// number, triangle count), the cost-model features, and CSR validation.
+// number, peel round, triangle count), the cost-model features, and CSR
+// validation.
 // All integer work; bound by HBM/L2 gathers over the adjacency.
 
 #include <math.h>
@@ -30,75 +31,35 @@ __global__ void k_degree(uint64_t n, const uint64_t* __restrict__ rp, uint64_t* 
   if (v < n) metric[v] = rp[v + 1] - rp[v];
 }
 
-// --- core numbers: level-synchronous peeling --------------------------------
-// ctl: [0] level k, [1] removed in this round, [2] min remaining degree seen,
-//      [3] vertices remaining.
+// --- peeling: core numbers and peel rounds -----------------------------------
+// Level-synchronous peeling.  Level k starts at 0.  A round removes, all at
+// once, every remaining vertex whose remaining degree is <= k; a round that
+// would remove nobody instead raises k to the smallest remaining degree.  A
+// round is two kernels: k_peel_mark decides who leaves from the degrees at the
+// start of the round and lists the leavers, then k_peel_drop takes them out of
+// their neighbours' degrees, one wave per leaver.  Each vertex gets either the
+// level it left at (its core number) or the index of its round (the peel
+// order); both depend on the graph only, not on the order in which waves run.
+// ctl: [0] level k, [1] leavers in this round (length of the list),
+//      [2] smallest remaining degree seen, [3] vertices remaining,
+//      [4] round index.
 constexpr uint64_t kAlive = ~0ULL;
 
-__global__ void k_core_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_t* deg, uint64_t* core,
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    uint32_t o = __shfl_xor(v, m, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__global__ void k_peel_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_t* deg, uint64_t* out,
                             uint64_t* ctl) {
   uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (v < n) {
     deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
-    core[v] = kAlive;
-  }
-  if (v == 0) {
-    ctl[0] = 0;
-    ctl[1] = 0;
-    ctl[2] = ~0ULL;
-    ctl[3] = n;
-  }
-}
-
-// One round at level k: every alive vertex of remaining degree <= k leaves
-// with core number k and decrements its alive neighbours.  A vertex whose
-// degree drops to <= k during the round leaves in the next round.
-__global__ void k_core_round(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
-                             uint32_t* deg, uint64_t* core, uint64_t* ctl) {
-  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const uint64_t k = ctl[0];
-  bool removed = false;
-  if (v < n && core[v] == kAlive) {
-    uint32_t d = __hip_atomic_load(&deg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (d <= k) {
-      core[v] = k;
-      removed = true;
-      for (uint64_t i = rp[v]; i < rp[v + 1]; ++i) {
-        uint32_t w = col[i];
-        if (core[w] == kAlive) atomicSub(&deg[w], 1u);
-      }
-    } else {
-      atomicMin((unsigned long long*)&ctl[2], (unsigned long long)d);
-    }
-  }
-  uint64_t cnt = __popcll(ballot(removed));
-  if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)cnt);
-}
-
-// After a round: if nobody left, every alive degree is exact and > k, so the
-// next level is the smallest of them.
-__global__ void k_core_advance(uint64_t* ctl) {
-  uint64_t removed = ctl[1];
-  ctl[3] -= removed;
-  if (removed == 0 && ctl[3] > 0) ctl[0] = ctl[2];
-  ctl[1] = 0;
-  ctl[2] = ~0ULL;
-}
-
-// --- peel rounds: the degeneracy ordering taken in synchronous rounds -------
-// Same levels as the core peeling above, but a round is split in two kernels:
-// k_peel_mark decides who leaves from the degrees at the start of the round,
-// and only then k_peel_drop takes the leaving vertices out of their
-// neighbours' degrees.  The round a vertex leaves in is therefore fixed by the
-// graph alone, not by the order in which waves run.
-// ctl: [0] level k, [1] removed in this round, [2] min remaining degree seen,
-//      [3] vertices remaining, [4] round index.
-__global__ void k_peel_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_t* deg, uint64_t* round,
-                            uint64_t* ctl) {
-  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (v < n) {
-    deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
-    round[v] = kAlive;
+    out[v] = kAlive;
   }
   if (v == 0) {
     ctl[0] = 0;
@@ -109,30 +70,49 @@ __global__ void k_peel_init(uint64_t n, const uint64_t* __restrict__ rp, uint32_
   }
 }
 
-__global__ void k_peel_mark(uint64_t n, const uint32_t* __restrict__ deg, uint64_t* round, uint64_t* ctl) {
+// out[v] = level (core numbers) or round index (peel order) of each leaver;
+// leavers go to list[0 .. ctl[1]).
+__global__ void k_peel_mark(uint64_t n, const uint32_t* __restrict__ deg, uint64_t* out, uint32_t* list,
+                            uint64_t* ctl, int store_level) {
   uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t k = ctl[0];
-  bool removed = false;
-  if (v < n && round[v] == kAlive) {
+  bool leave = false;
+  uint32_t stay = ~0u;  // degree of a vertex that stays, for the next level
+  if (v < n && out[v] == kAlive) {
     uint32_t d = deg[v];
-    if (d <= k) {
-      round[v] = ctl[4];
-      removed = true;
-    } else {
-      atomicMin((unsigned long long*)&ctl[2], (unsigned long long)d);
-    }
+    if (d <= k) leave = true;
+    else stay = d;
   }
-  uint64_t cnt = __popcll(ballot(removed));
-  if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)cnt);
+  // one atomic per wave on the shared control words
+  stay = wave_min_u32(stay);
+  const uint64_t mask = ballot(leave);
+  uint64_t base = 0;
+  if (lane_id() == 0) {
+    if (mask) base = atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(mask));
+    if (stay != ~0u) atomicMin((unsigned long long*)&ctl[2], (unsigned long long)stay);
+  }
+  base = readlane64(base, 0);
+  if (leave) {
+    out[v] = store_level ? k : ctl[4];
+    list[base + mask_prefix(mask, lane_id())] = (uint32_t)v;
+  }
 }
 
-__global__ void k_peel_drop(uint64_t n, const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
-                            uint32_t* deg, const uint64_t* __restrict__ round, const uint64_t* __restrict__ ctl) {
-  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (v >= n || ctl[1] == 0 || round[v] != ctl[4]) return;
-  for (uint64_t i = rp[v]; i < rp[v + 1]; ++i) {
-    uint32_t w = col[i];
-    if (round[w] == kAlive) atomicSub(&deg[w], 1u);
+// One wave per leaver, lanes over its neighbours: a hub's neighbourhood is
+// spread over the wave instead of one lane walking it.
+__global__ void k_peel_drop(const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col, uint32_t* deg,
+                            const uint64_t* __restrict__ out, const uint32_t* __restrict__ list,
+                            const uint64_t* __restrict__ ctl) {
+  const uint64_t cnt = ctl[1];
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const int lane = lane_id();
+  for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave; i < cnt; i += waves) {
+    const uint32_t v = list[i];
+    const uint64_t e = rp[v + 1];
+    for (uint64_t j = rp[v] + lane; j < e; j += kWave) {
+      uint32_t w = col[j];
+      if (out[w] == kAlive) atomicSub(&deg[w], 1u);
+    }
   }
 }
 
@@ -253,19 +233,23 @@ hipError_t launch_root_metric(uint64_t n, const uint64_t* rp, const uint32_t* co
   return hipGetLastError();
 }
 
-int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg,
-                     uint64_t* ctl, hipStream_t s) {
+namespace {
+
+int run_peel(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* out, uint32_t* deg, uint32_t* list,
+             uint64_t* ctl, int store_level, hipStream_t s) {
   if (n == 0) return MCE_OK;
   const uint32_t g = blocks_for(n, 256);
-  hipLaunchKernelGGL(k_core_init, dim3(g), dim3(256), 0, s, n, rp, deg, core, ctl);
+  const uint32_t gd = std::min<uint32_t>(g, 2048);
+  hipLaunchKernelGGL(k_peel_init, dim3(g), dim3(256), 0, s, n, rp, deg, out, ctl);
   MCE_TRY_HIP(hipGetLastError());
-  // Rounds are enqueued in groups; the host only reads the remaining count
-  // between groups.  Extra rounds after the last vertex left are no-ops.
+  // Rounds are enqueued in growing groups; the host reads the remaining count
+  // only between groups.  Rounds after the last vertex left change nothing.
   uint32_t group = 16;
   for (;;) {
     for (uint32_t r = 0; r < group; ++r) {
-      hipLaunchKernelGGL(k_core_round, dim3(g), dim3(256), 0, s, n, rp, col, deg, core, ctl);
-      hipLaunchKernelGGL(k_core_advance, dim3(1), dim3(1), 0, s, ctl);
+      hipLaunchKernelGGL(k_peel_mark, dim3(g), dim3(256), 0, s, n, deg, out, list, ctl, store_level);
+      hipLaunchKernelGGL(k_peel_drop, dim3(gd), dim3(256), 0, s, rp, col, deg, out, list, ctl);
+      hipLaunchKernelGGL(k_peel_advance, dim3(1), dim3(1), 0, s, ctl);
     }
     MCE_TRY_HIP(hipGetLastError());
     uint64_t remaining = 0;
@@ -277,29 +261,16 @@ int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64
   return MCE_OK;
 }
 
+}  // namespace
+
+int run_core_numbers(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* core, uint32_t* deg,
+                     uint32_t* list, uint64_t* ctl, hipStream_t s) {
+  return run_peel(n, rp, col, core, deg, list, ctl, 1, s);
+}
+
 int run_peel_rounds(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* round, uint32_t* deg,
-                    uint64_t* ctl, hipStream_t s) {
-  if (n == 0) return MCE_OK;
-  const uint32_t g = blocks_for(n, 256);
-  hipLaunchKernelGGL(k_peel_init, dim3(g), dim3(256), 0, s, n, rp, deg, round, ctl);
-  MCE_TRY_HIP(hipGetLastError());
-  // As for the core numbers: rounds go out in growing groups, and rounds after
-  // the last vertex left change nothing.
-  uint32_t group = 16;
-  for (;;) {
-    for (uint32_t r = 0; r < group; ++r) {
-      hipLaunchKernelGGL(k_peel_mark, dim3(g), dim3(256), 0, s, n, deg, round, ctl);
-      hipLaunchKernelGGL(k_peel_drop, dim3(g), dim3(256), 0, s, n, rp, col, deg, round, ctl);
-      hipLaunchKernelGGL(k_peel_advance, dim3(1), dim3(1), 0, s, ctl);
-    }
-    MCE_TRY_HIP(hipGetLastError());
-    uint64_t remaining = 0;
-    MCE_TRY_HIP(hipMemcpyAsync(&remaining, ctl + 3, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    MCE_TRY_HIP(hipStreamSynchronize(s));
-    if (remaining == 0) break;
-    if (group < 256) group *= 2;
-  }
-  return MCE_OK;
+                    uint32_t* list, uint64_t* ctl, hipStream_t s) {
+  return run_peel(n, rp, col, round, deg, list, ctl, 0, s);
 }
 
 hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s) {
