@@ -330,11 +330,16 @@ __device__ uint64_t split_root(const EnumArgs& a, Lds& L, uint64_t* fr, uint32_t
 }
 
 // K is maximal: count it, hash it, and optionally write it out.
+__device__ void store_clique(const EnumArgs& a, uint32_t k, const uint32_t* kG);
+
 __device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, const uint32_t* kG) {
-  const int lane = lane_id();
   ++acc.tc;
   acc.th += clique_term(zsum, k);
-  if (!a.cl_vert) return;
+  if (a.cl_vert) store_clique(a, k, kG);
+}
+
+__device__ void store_clique(const EnumArgs& a, uint32_t k, const uint32_t* kG) {
+  const int lane = lane_id();
   uint64_t old = 0;
   if (lane == 0) old = fetch_add(&a.ctl[CTL_CLQ], (1ULL << 32) | k);
   old = readlane64(old, 0);
@@ -354,6 +359,41 @@ __device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, con
 
 // --- compact path ------------------------------------------------------------
 
+// The compact search is bound by scalar issue (one scalar instruction per CU
+// per cycle) while the vector unit has room, so its tallies live in vector
+// registers: every lane holds the same value.  A zero the compiler cannot see
+// through moves the arithmetic that depends on it to the vector unit.
+__device__ __forceinline__ uint64_t opaque_vzero64() {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return ((uint64_t)z << 32) | z;
+}
+
+// acc + popcount(x) on the vector unit, for a wave-uniform x.
+__device__ __forceinline__ uint32_t vbcnt_add(uint64_t x, uint32_t acc) {
+  uint32_t r, t;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(t) : "s"((uint32_t)x), "v"(acc));
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "s"((uint32_t)(x >> 32)), "v"(t));
+  return r;
+}
+
+struct VTally {
+  uint64_t vz;  // opaque zero
+  uint64_t tn, tc, th, ss, es;
+  __device__ void node() { tn += 1; }
+  __device__ void clique(uint64_t zsum, uint32_t k) {
+    tc += 1;
+    th += clique_term(zsum + vz, k);
+  }
+  __device__ void flush(Acc& acc) const {
+    acc.tn += readlane64(tn, 0);
+    acc.tc += readlane64(tc, 0);
+    acc.th += readlane64(th, 0);
+    acc.ssum += readlane64(ss, 0);
+    acc.esum += readlane64(es, 0);
+  }
+};
+
 template <bool EXCL, class LT>
 __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t s, uint64_t P, uint64_t Xp,
                             uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand, uint32_t kbase,
@@ -362,14 +402,20 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
   const int lane = lane_id();
   uint32_t d = 0;       // frames on the stack
   uint32_t kl = kbase;  // |K| of the current node (a last child reuses its parent's frame slot)
-  const uint64_t tn0 = acc.tn, t0 = now();
+  const uint64_t t0 = now();
+  VTally T;
+  T.vz = opaque_vzero64();
+  T.tn = T.tc = T.th = T.ss = T.es = T.vz;
   for (;;) {
     bool pop = false;
     if (expand) {
       expand = false;
-      ++acc.tn;
+      T.node();
       if (P == 0) {
-        if ((Xp | Xx) == 0) emit(a, acc, zsum, kl, L.kG);
+        if ((Xp | Xx) == 0) {
+          T.clique(zsum, kl);
+          if (a.cl_vert) store_clique(a, kl, L.kG);
+        }
         pop = true;
       } else {
         const uint64_t mP = P | Xp;
@@ -383,9 +429,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         else
           prow = readlane64(c.rowXP, row & 63);
         ext = P & ~prow;
-        const uint64_t sm = (uint64_t)__popcll(P) + __popcll(Xp) + __popcll(Xx);
-        acc.ssum += sm;
-        acc.esum += (uint64_t)__popcll(ext);
+        T.ss += vbcnt_add(Xx, vbcnt_add(Xp, vbcnt_add(P, (uint32_t)T.vz)));
+        T.es += vbcnt_add(ext, (uint32_t)T.vz);
       }
     }
     if (!pop && ext) {
@@ -406,13 +451,14 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       if (cP == 0) {
         // the child is a leaf (its cand is empty): one node, maximal iff its
         // fini is empty too; no frame needed
-        ++acc.tn;
+        T.node();
         if (((Xp & rq) | (Xx & rqx)) == 0) {
+          T.clique(zsum + readlane64(c.zP, q), kl + 1);
           if (a.cl_vert) {
             if (lane == 0) L.kG[kl] = readlane32(c.gP, q);
             __syncthreads();  // the K list is read by every lane
+            store_clique(a, kl + 1, L.kG);
           }
-          emit(a, acc, zsum + readlane64(c.zP, q), kl + 1, L.kG);
         }
         continue;
       }
@@ -425,22 +471,23 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         const uint32_t w = (uint32_t)__builtin_ctzll(cP);
         const uint64_t rw = readlane64(c.rowPP, w), rwx = readlane64(c.rowPX, w);
         const uint64_t cXp = Xp & rq, cXx = Xx & rqx;
-        ++acc.tn;
+        T.node();
         const bool blocked = ((cXp & rw) | (cXx & rwx)) != 0;
         const bool excluded = EXCL && (((F | readlane64(c.rowEx, q)) >> w) & 1ULL);
         // the child's pivot step, as the op count of an expanded node
-        acc.ssum += 1 + (uint64_t)__popcll(cXp) + (uint64_t)__popcll(cXx);
-        acc.esum += blocked ? 0u : 1u;
+        T.ss += vbcnt_add(cXx, vbcnt_add(cXp, (uint32_t)T.vz + 1u));
+        if (!blocked) T.es += 1;
         if (!blocked && !excluded) {
-          ++acc.tn;
+          T.node();
+          T.clique(zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2);
           if (a.cl_vert) {
             if (lane == 0) {
               L.kG[kl] = readlane32(c.gP, q);
               L.kG[kl + 1] = readlane32(c.gP, w);
             }
             __syncthreads();  // the K list is read by every lane
+            store_clique(a, kl + 2, L.kG);
           }
-          emit(a, acc, zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2, L.kG);
         }
         continue;
       }
@@ -526,7 +573,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
     }
     // pop
     if (d == 0) {
-      dg.cnodes += acc.tn - tn0;
+      dg.cnodes += readlane64(T.tn, 0);
+      T.flush(acc);
       dg.t_compact += now() - t0;
       return;
     }
@@ -1068,7 +1116,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
 // pool block).  Its register footprint is a fraction of k_enum's, so many
 // more waves fit per SIMD to hide the latency of the search's serial chain.
 template <bool EXCL>
-__global__ void __launch_bounds__(64) k_compact(EnumArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_compact(EnumArgs a) {
   __shared__ LdsC L;
   const int lane = threadIdx.x;
   uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
