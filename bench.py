@@ -357,6 +357,22 @@ def measured_traffic(ops_per_launch):
     return t.get("bytes_per_call")
 
 
+def measured_issue():
+    """Scalar and vector instruction issue of k_compact as fractions of the
+    per-CU issue ceiling, from the committed SQ counter summary, or None when
+    the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "sq_cl1m_communities_degree.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources") != kernel_sources_digest():
+        return None
+    k = t["per_kernel"]["k_compact"]
+    return {"kernel": "k_compact", "salu_frac": k["salu_frac"], "valu_frac": k["valu_frac"],
+            "peak_per_s": t["peak_issue_per_s"], "unit": "wave instructions/s per class (SQ_INSTS_SALU, SQ_INSTS_VALU)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +456,8 @@ def main():
                      "traffic": measured_traffic(r0["alg_ops"]),
                      "traffic_unit": "bytes per call (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)",
                      "kernel": "k_enum + k_compact (the enumeration: both launches)",
-                     "ops_per_launch": r0["alg_ops"]},
+                     "ops_per_launch": r0["alg_ops"],
+                     "issue": measured_issue()},
     }
     if not args.no_ownership:
         log("ownership ranks and imbalance ...")

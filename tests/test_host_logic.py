@@ -54,3 +54,18 @@ def test_bench_traffic_is_tied_to_the_kernel_sources(monkeypatch):
         assert bench.measured_traffic(None) == rec["bytes_per_call"]
     monkeypatch.setattr(bench, "kernel_sources_digest", lambda: "0" * 16)
     assert bench.measured_traffic(None) is None
+
+
+def test_bench_issue_fractions_are_tied_to_the_kernel_sources(monkeypatch):
+    import json
+    import os
+    import bench
+    path = os.path.join(bench.ROOT, "profiles", "sq_cl1m_communities_degree.json")
+    with open(path) as f:
+        rec = json.load(f)
+    if rec["kernel_sources"] == bench.kernel_sources_digest():
+        got = bench.measured_issue()
+        assert got["salu_frac"] == rec["per_kernel"]["k_compact"]["salu_frac"]
+        assert 0 < got["salu_frac"] < 1.05 and 0 < got["valu_frac"] < 1.05
+    monkeypatch.setattr(bench, "kernel_sources_digest", lambda: "0" * 16)
+    assert bench.measured_issue() is None
