@@ -403,6 +403,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
   uint32_t d = 0;       // frames on the stack
   uint32_t kl = kbase;  // |K| of the current node (a last child reuses its parent's frame slot)
   const uint64_t t0 = now();
+  const uint32_t dlim = 4 * a.donate_interval;
   VTally T;
   T.vz = opaque_vzero64();
   T.tn = T.tc = T.th = T.ss = T.es = T.vz;
@@ -436,7 +437,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
     if (!pop && ext) {
       const uint32_t q = (uint32_t)__builtin_ctzll(ext);
       const uint64_t qb = 1ULL << q;
-      ext &= ext - 1;
+      ext &= ~qb;
       if (EXCL && (F & qb)) {
         // K u {q} would contain an excluded edge: q moves to fini unvisited
         P &= ~qb;
@@ -462,7 +463,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         }
         continue;
       }
-      if ((cP & (cP - 1)) == 0) {
+      if (__popcll(cP) == 1) {
         // the child has one candidate w.  Every t_u of the child is 0 or 1:
         // if a fini vertex is adjacent to w it is the pivot and ext is empty
         // (one node); else ext = {w} and the grandchild K+q+w has empty cand
@@ -515,7 +516,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       zsum += readlane64(c.zP, q);
       expand = true;
 
-      if (can_donate && ++since >= 4 * a.donate_interval) {
+      if (can_donate && ++since >= dlim) {
         since = 0;
         const uint64_t td = now();
         for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
