@@ -408,7 +408,6 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
   T.vz = opaque_vzero64();
   T.tn = T.tc = T.th = T.ss = T.es = T.vz;
   for (;;) {
-    bool pop = false;
     if (expand) {
       expand = false;
       T.node();
@@ -417,7 +416,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
           T.clique(zsum, kl);
           if (a.cl_vert) store_clique(a, kl, L.kG);
         }
-        pop = true;
+        ext = 0;  // no children: the node is done
       } else {
         const uint64_t mP = P | Xp;
         const uint32_t k1 = ((mP >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP) : 0u;
@@ -434,7 +433,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         T.es += vbcnt_add(ext, (uint32_t)T.vz);
       }
     }
-    if (!pop && ext) {
+    while (ext) {
       const uint32_t q = (uint32_t)__builtin_ctzll(ext);
       const uint64_t qb = 1ULL << q;
       ext &= ~qb;
@@ -570,8 +569,9 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         }
         dg.t_donate += now() - td;
       }
-      continue;
+      break;  // descend into the child
     }
+    if (expand) continue;
     // pop
     if (d == 0) {
       dg.cnodes += readlane64(T.tn, 0);
