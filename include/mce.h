@@ -175,7 +175,8 @@ typedef struct {
 /* All maximal cliques of `g` (Algorithm 4 over Algorithm 1).
  * opts may be NULL (defaults), cliques and per_vertex may be NULL.
  * Supported envelope: n < 2^32, |cand| of every subproblem <= 4096 (else
- * MCE_ENOTSUP), and for materialised output n_verts < 2^32. */
+ * MCE_ENOTSUP; cliques up to 4097 vertices are then found), and for
+ * materialised output n_verts < 2^32. */
 int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
                mce_clique_buf* cliques, const mce_per_vertex* per_vertex);
 
@@ -213,7 +214,12 @@ int imce_create(const mce_csr* g, const mce_opts* opts, imce_state** out, mce_re
  * repeated in the batch are skipped (n_skipped); the survivors, in input
  * order, are e_1..e_rho of Algorithm 5.  new_cl / del_cl (nullable) receive
  * Lambda_new / Lambda_del.  On any error the state is unchanged (the batch is
- * applied atomically). */
+ * applied atomically).
+ * Supported envelope (else MCE_ENOTSUP): every batch edge has at most 4096
+ * common neighbours in G+H; a new clique holds at most 256 batch edges and
+ * splits into at most 1024 subsets free of batch edges (Algorithm 7); a new
+ * clique of more than 64 vertices has at most 64 vertices that are ends of
+ * batch edges inside it. */
 int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
                    imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
 

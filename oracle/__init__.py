@@ -26,6 +26,8 @@ RANK_DEGREE = 0
 RANK_DEGENERACY = 1
 RANK_TRIANGLE = 2
 RANK_PEEL = 3
+HIST_LEN = 4097  # clique-size histogram entries: sizes 0..4095, then >= 4096
+
 RANKS = {"degree": RANK_DEGREE, "degeneracy": RANK_DEGENERACY, "triangle": RANK_TRIANGLE, "peel": RANK_PEEL}
 
 
@@ -72,7 +74,8 @@ def lib():
         L.orc_mce_ttt_root.argtypes = [ctypes.c_uint64, P64, P32, ctypes.POINTER(_Result), ctypes.POINTER(_Cliques)]
         L.orc_mce_brute.argtypes = [ctypes.c_uint64, P64, P32, ctypes.POINTER(_Result), ctypes.POINTER(_Cliques)]
         L.orc_mce_parmce.argtypes = [ctypes.c_uint64, P64, P32, ctypes.c_int, P32, ctypes.c_uint64, ctypes.c_int,
-                                     ctypes.POINTER(_Result), P64, P64, P64, ctypes.POINTER(_Cliques)]
+                                     ctypes.POINTER(_Result), P64, P64, P64, ctypes.POINTER(_Cliques), P64,
+                                     ctypes.c_uint64]
         L.orc_imce_create.restype = ctypes.c_void_p
         L.orc_imce_create.argtypes = [ctypes.c_uint64, P64, P32, ctypes.c_int]
         L.orc_imce_destroy.argtypes = [ctypes.c_void_p]
@@ -158,8 +161,9 @@ def mce_brute(g, cliques: bool = False):
 class ParMCE:
     """Result of the per-vertex decomposition (Algorithm 4)."""
 
-    def __init__(self, count, set_hash, nodes, nodes_v, count_v, hash_v, cliques, verts):
+    def __init__(self, count, set_hash, nodes, nodes_v, count_v, hash_v, cliques, verts, sizes):
         self.count, self.set_hash, self.nodes = count, set_hash, nodes
+        self.sizes = sizes  # sizes[k] = maximal cliques with k vertices (last entry: k >= len-1)
         self.nodes_v, self.count_v, self.hash_v = nodes_v, count_v, hash_v
         self.cliques = cliques
         self.verts = verts
@@ -174,17 +178,18 @@ def mce_parmce(g, rank: str = "degree", verts: Optional[np.ndarray] = None, thre
     nodes_v = np.zeros(max(k, 1), dtype=np.uint64)
     count_v = np.zeros(max(k, 1), dtype=np.uint64)
     hash_v = np.zeros(max(k, 1), dtype=np.uint64)
+    sizes = np.zeros(HIST_LEN, dtype=np.uint64)
 
     def call(c):
         return lib().orc_mce_parmce(g.n, _p64(rp), _p32(col), RANKS[rank], _p32(vs), k, threads, ctypes.byref(r),
-                                    _p64(nodes_v), _p64(count_v), _p64(hash_v), c)
+                                    _p64(nodes_v), _p64(count_v), _p64(hash_v), c, _p64(sizes), HIST_LEN)
 
     cl = None
     if cliques:
         cl = sorted(_collect(lambda c: call(ctypes.byref(c))))
     else:
         call(None)
-    return ParMCE(r.count, r.set_hash, r.nodes, nodes_v[:k], count_v[:k], hash_v[:k], cl, vs)
+    return ParMCE(r.count, r.set_hash, r.nodes, nodes_v[:k], count_v[:k], hash_v[:k], cl, vs, sizes)
 
 
 class Imce:

@@ -151,11 +151,14 @@ struct Sink {
   uint64_t count = 0, hash = 0, nodes = 0;
   bool keep = false;
   std::vector<VSet> cliques;
+  std::vector<uint64_t> sizes;  // sizes[k] = number of maximal cliques with k vertices (Section 6.1, Figure 5)
   void emit(const std::vector<uint32_t>& K) {
     VSet c = K;
     std::sort(c.begin(), c.end());
     count += 1;
     hash += clique_hash(c.data(), c.size());
+    if (sizes.size() <= c.size()) sizes.resize(c.size() + 1, 0);
+    sizes[c.size()] += 1;
     if (keep) cliques.push_back(std::move(c));
   }
 };
@@ -433,9 +436,13 @@ int orc_mce_ttt_root(uint64_t n, const uint64_t* rp, const uint32_t* col, orc_re
 // sequentially (optionally by `nthreads` threads that pull vertices from a
 // shared counter; sums are commutative so the merge is exact).  `verts`
 // restricts the run to a subset of the subproblems (NULL = all n).
+//
+// `size_hist` (nullable, `hist_len` entries): size_hist[k] = number of maximal
+// cliques with k vertices (sizes >= hist_len are added to the last entry), the
+// distribution the paper plots per input graph (Section 6.1).
 int orc_mce_parmce(uint64_t n, const uint64_t* rp, const uint32_t* col, int kind, const uint32_t* verts,
                    uint64_t nverts, int nthreads, orc_result* res, uint64_t* nodes_v, uint64_t* count_v,
-                   uint64_t* hash_v, CliqueOut* out) {
+                   uint64_t* hash_v, CliqueOut* out, uint64_t* size_hist, uint64_t hist_len) {
   Adj A = adj_from_csr(n, rp, col);
   std::vector<uint64_t> metric = metric_of(A, kind);
   uint64_t total = verts ? nverts : n;
@@ -465,10 +472,14 @@ int orc_mce_parmce(uint64_t n, const uint64_t* rp, const uint32_t* col, int kind
   }
   orc_result r{0, 0, 0};
   std::vector<VSet> all;
+  if (size_hist)
+    for (uint64_t k = 0; k < hist_len; ++k) size_hist[k] = 0;
   for (Sink& s : sinks) {
     r.count += s.count;
     r.set_hash += s.hash;
     r.nodes += s.nodes;
+    if (size_hist && hist_len)
+      for (uint64_t k = 0; k < s.sizes.size(); ++k) size_hist[std::min(k, hist_len - 1)] += s.sizes[k];
     if (out) for (auto& c : s.cliques) all.push_back(std::move(c));
   }
   *res = r;

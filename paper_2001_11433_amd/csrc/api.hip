@@ -254,6 +254,11 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     a.cl_vert = j.cl_vert;
     a.cap_cliques = j.cap_cliques;
     a.cap_verts = j.cap_verts;
+    if (j.max_p + (j.excl ? 2u : 1u) + 2 > kKLds) {
+      // some clique may outgrow the LDS K list: one global list per wave
+      MCE_TRY(w.kbig.ensure((uint64_t)grid * kKBig * sizeof(uint32_t)));
+      a.kbig = w.kbig.as<uint32_t>();
+    }
     const bool handoff = !opts.inline_compact;
     uint64_t hand_cap = 0;
     if (handoff) {
@@ -554,7 +559,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     cl->n_cliques = nc;
     cl->n_verts = nv;
     if (ctl[CTL_FLAGS] & 2ULL) {
-      set_error("materialised output exceeds 2^32 vertices or a clique exceeds 1024 vertices");
+      set_error("materialised output exceeds 2^32 vertices");
       return MCE_ENOTSUP;
     }
     if (nc > cl->cap_cliques || nv > cl->cap_verts || !cl_off) {

@@ -36,7 +36,6 @@ namespace mce {
 
 namespace {
 
-constexpr uint32_t kKMax = 512;       // largest clique (|K| bound of the K list)
 constexpr uint32_t kLdsWords = 1024;  // per-wave LDS stack of the wide path: 8 KiB
 constexpr uint32_t kCF = 8;           // words per compact frame
 constexpr uint32_t kCFrames = 66;     // compact depth <= 64 below the re-based node
@@ -49,7 +48,7 @@ constexpr uint32_t kCR_PP = 10, kCR_XP = 74, kCR_PX = 138, kCR_EX = 202, kCR_KEY
 struct Lds {
   uint64_t sP[64];
   uint64_t cstk[kCFrames * kCF];
-  uint32_t kG[kKMax];  // ids of K, roots first
+  uint32_t kG[kKLds];  // ids of K, roots first
   uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
 };
 
@@ -219,6 +218,7 @@ __device__ void publish_record(const EnumArgs& a, uint32_t blk) {
 // can be donated while the wave works deeper (also from the compact path).
 struct WideCtx {
   uint64_t* stk;
+  const uint32_t* kG;  // the task's K list (LDS or the wave's global region)
   uint32_t F, wp, base, top, s, kroot;
 };
 
@@ -250,6 +250,7 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
   if (blk == kNil) return false;
   uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
   const uint64_t* fi = w.stk + (uint64_t)i * w.F;
+  __syncthreads();  // K entries written by single lanes, possibly in global memory
   if (lane == 0) {
     rec[R_S] = w.s;
     rec[R_TYPE] = 0;
@@ -264,7 +265,7 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
     rec[R_HDR + O_EXT + lane] = rest;
   }
   for (uint32_t k = 3 * w.wp + lane; k < w.F; k += kWave) rec[R_HDR + k] = fi[k];
-  for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + R_HDR + w.F))[j] = L.kG[j];
+  for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + R_HDR + w.F))[j] = w.kG[j];
   if (lane < (int)w.wp) w.stk[(uint64_t)i * w.F + O_EXT + lane] = km;
   publish_record(a, blk);
   __threadfence_block();
@@ -279,7 +280,7 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
 // formula), so the recursion tree is unchanged.  `fr` is the root frame with
 // its fini words already in place; returns this lane's word of the kept ext.
 template <bool EXCL>
-__device__ uint64_t split_root(const EnumArgs& a, Lds& L, uint64_t* fr, uint32_t F, uint32_t wp, uint32_t s,
+__device__ uint64_t split_root(const EnumArgs& a, const uint32_t* kG, uint64_t* fr, uint32_t F, uint32_t wp, uint32_t s,
                                uint32_t kroot, uint64_t rP, uint64_t rXp, uint64_t rExt, uint64_t rF, uint64_t zsum,
                                uint32_t k, bool& can_donate) {
   const int lane = lane_id();
@@ -322,7 +323,7 @@ __device__ uint64_t split_root(const EnumArgs& a, Lds& L, uint64_t* fr, uint32_t
       rec[R_HDR + O_EXT + lane] = chunk;
     }
     for (uint32_t q = 3 * wp + lane; q < F; q += kWave) rec[R_HDR + q] = fr[q];
-    for (uint32_t q = lane; q < kroot; q += kWave) ((uint32_t*)(rec + R_HDR + F))[q] = L.kG[q];
+    for (uint32_t q = lane; q < kroot; q += kWave) ((uint32_t*)(rec + R_HDR + F))[q] = kG[q];
     publish_record(a, blk);
     keep &= below;
   }
@@ -340,11 +341,12 @@ __device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, con
 
 __device__ void store_clique(const EnumArgs& a, uint32_t k, const uint32_t* kG) {
   const int lane = lane_id();
+  __syncthreads();  // K entries written by single lanes, possibly in global memory
   uint64_t old = 0;
   if (lane == 0) old = fetch_add(&a.ctl[CTL_CLQ], (1ULL << 32) | k);
   old = readlane64(old, 0);
   const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
-  if (pos + k > 0xFFFFFFFFULL || k > kKMax) {
+  if (pos + k > 0xFFFFFFFFULL || k > kKBig) {
     if (lane == 0) atomicOr((unsigned long long*)&a.ctl[CTL_FLAGS], 2ULL);
     return;
   }
@@ -394,12 +396,15 @@ struct VTally {
   }
 };
 
-template <bool EXCL, class LT>
-__device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t s, uint64_t P, uint64_t Xp,
-                            uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand, uint32_t kbase,
-                            uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since, const WideCtx* wide,
-                            Diag& dg) {
+// BIGK: the K list lives in the wave's global region `gK` instead of LDS
+// (subproblems whose cliques can reach the LDS list's length).
+template <bool EXCL, bool BIGK, class LT>
+__device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
+                            uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand,
+                            uint32_t kbase, uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since,
+                            const WideCtx* wide, Diag& dg) {
   const int lane = lane_id();
+  uint32_t* const kG = BIGK ? gK : L.kG;
   uint32_t d = 0;       // frames on the stack
   uint32_t kl = kbase;  // |K| of the current node (a last child reuses its parent's frame slot)
   const uint64_t t0 = now();
@@ -414,7 +419,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
       if (P == 0) {
         if ((Xp | Xx) == 0) {
           T.clique(zsum, kl);
-          if (a.cl_vert) store_clique(a, kl, L.kG);
+          if (a.cl_vert) store_clique(a, kl, kG);
         }
         ext = 0;  // no children: the node is done
       } else {
@@ -455,9 +460,9 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         if (((Xp & rq) | (Xx & rqx)) == 0) {
           T.clique(zsum + readlane64(c.zP, q), kl + 1);
           if (a.cl_vert) {
-            if (lane == 0) L.kG[kl] = readlane32(c.gP, q);
+            if (lane == 0) kG[kl] = readlane32(c.gP, q);
             __syncthreads();  // the K list is read by every lane
-            store_clique(a, kl + 1, L.kG);
+            store_clique(a, kl + 1, kG);
           }
         }
         continue;
@@ -482,11 +487,11 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
           T.clique(zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2);
           if (a.cl_vert) {
             if (lane == 0) {
-              L.kG[kl] = readlane32(c.gP, q);
-              L.kG[kl + 1] = readlane32(c.gP, w);
+              kG[kl] = readlane32(c.gP, q);
+              kG[kl + 1] = readlane32(c.gP, w);
             }
             __syncthreads();  // the K list is read by every lane
-            store_clique(a, kl + 2, L.kG);
+            store_clique(a, kl + 2, kG);
           }
         }
         continue;
@@ -506,7 +511,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
         }
         ++d;
       }
-      if (lane == 0) L.kG[kl] = readlane32(c.gP, q);
+      if (lane == 0) kG[kl] = readlane32(c.gP, q);
       ++kl;
       P = cP;
       Xp &= rq;
@@ -557,7 +562,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, const Compact& c, uint32_t
               if (EXCL) rec[kCR_EX + lane] = c.rowEx;
               rec[kCR_KEY + lane] = (uint64_t)c.keyP | ((uint64_t)c.keyX << 32);
               ((uint32_t*)(rec + kCR_GP))[lane] = c.gP;
-              for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = L.kG[j];
+              if (BIGK) __syncthreads();  // K entries written by single lanes in global memory
+              for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = kG[j];
               if (lane == 0) L.cstk[i * kCF + 3] = km;
               publish_record(a, blk);
             } else {
@@ -615,8 +621,8 @@ __device__ void compact_keys(Compact& c) {
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
 }
 
-template <bool EXCL, class LT>
-__device__ void compact_from_record(const uint64_t* rec, Compact& c, LT& L, uint64_t& P, uint64_t& Xp,
+template <bool EXCL>
+__device__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* kG, uint64_t& P, uint64_t& Xp,
                                     uint64_t& Xx, uint64_t& ext, uint64_t& zsum, uint64_t& F, uint32_t& klen) {
   const int lane = lane_id();
   const uint64_t hdr = readlane64(rec[R_DEPTH], 0);
@@ -632,7 +638,7 @@ __device__ void compact_from_record(const uint64_t* rec, Compact& c, LT& L, uint
   c.keyX = (uint32_t)(key >> 32);
   c.gP = ((const uint32_t*)(rec + kCR_GP))[lane];
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
-  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
+  for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
   const uint64_t v = lane < 6 ? rec[R_HDR + lane] : 0;
   P = readlane64(v, 0);
   Xp = readlane64(v, 1);
@@ -656,7 +662,7 @@ __device__ __forceinline__ uint32_t hand_words(uint32_t np, uint32_t nx, uint32_
 // Reserves and writes one record; false when the arena or the index is full
 // (the request still counts, so the host learns the size it needs).
 template <bool EXCL>
-__device__ bool hand_off(const EnumArgs& a, const Lds& L, const Compact& c, uint32_t gX, uint32_t s, uint64_t F,
+__device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, const Compact& c, uint32_t gX, uint32_t s, uint64_t F,
                          uint64_t zsum, uint32_t klen) {
   const int lane = lane_id();
   const uint32_t np = c.np, nx = c.nx;
@@ -667,6 +673,7 @@ __device__ bool hand_off(const EnumArgs& a, const Lds& L, const Compact& c, uint
   const uint64_t idx = old >> 32, at = old & 0xFFFFFFFFULL;
   if (idx >= a.hand_cap || at + units > a.hand_units) return false;
   uint64_t* rec = a.hand + at * 8;
+  __syncthreads();  // K entries written by single lanes, possibly in global memory
   if (lane == 0) {
     rec[0] = (uint64_t)s | ((uint64_t)np << 32) | ((uint64_t)nx << 40);
     rec[1] = klen;
@@ -689,7 +696,7 @@ __device__ bool hand_off(const EnumArgs& a, const Lds& L, const Compact& c, uint
   uint32_t* u = (uint32_t*)w;
   if (lane < (int)np) u[lane] = c.gP;
   if (lane < (int)nx) u[np + lane] = gX;
-  for (uint32_t j = lane; j < klen; j += kWave) u[np + nx + j] = L.kG[j];
+  for (uint32_t j = lane; j < klen; j += kWave) u[np + nx + j] = kG[j];
   return true;
 }
 
@@ -734,6 +741,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   __shared__ Lds L;
   const int lane = threadIdx.x;
   uint64_t* const gstk = a.stacks + (uint64_t)blockIdx.x * a.stack_words;
+  uint32_t* const gK = a.kbig ? a.kbig + (uint64_t)blockIdx.x * kKBig : nullptr;
   uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
@@ -760,16 +768,26 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     const uint32_t wv = (p + x + 31) / 32;  // subproblem universe in 32-bit words
     Acc acc = {0, 0, 0, 0, 0};
     bool overflow = false;
+    // K list: LDS unless this subproblem's cliques (at most |K at the root| +
+    // p vertices) could outgrow it; then the wave's global region
+    const bool bigk = gK != nullptr && (EXCL ? 2u : 1u) + p + 2 > kKLds;
+    uint32_t* const kG = bigk ? gK : L.kG;
+    const uint32_t kcap = bigk ? kKBig : kKLds;
 
     if (rtype == 1) {
       // donated compact subtree
       Compact c;
       uint64_t P, Xp, Xx, ext, zsum, F;
       uint32_t klen;
-      compact_from_record<EXCL>(rec, c, L, P, Xp, Xx, ext, zsum, F, klen);
-      __threadfence_block();
+      compact_from_record<EXCL>(rec, c, kG, P, Xp, Xx, ext, zsum, F, klen);
+      __syncthreads();
       if (lane == 0) pool_push(a, blk);
-      compact_dfs<EXCL>(a, L, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since, nullptr, dg);
+      if (bigk)
+        compact_dfs<EXCL, true>(a, L, gK, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since,
+                                nullptr, dg);
+      else
+        compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since,
+                                 nullptr, dg);
     } else {
       const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
       const uint32_t F = 3 * wp + wf + wx + 1;
@@ -792,7 +810,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
         cap = (uint32_t)(a.stack_words / F);
       }
       const uint32_t base = cont ? (uint32_t)readlane64(rec[R_DEPTH], 0) : 0u;
-      overflow = base + 2 > cap || base + kroot >= kKMax;
+      overflow = base + 2 > cap || base + kroot >= kcap;
 
       uint64_t rP = 0, rXp = 0, rExt = 0, rF = 0, zsum = 0;
       uint32_t d = base;
@@ -805,17 +823,17 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
           for (uint32_t k = lane; k < wx; k += kWave) fr[O_XX + k] = full_word(x, k);
           const uint32_t r0 = readlane32(a.sub.r0[s], 0);
           zsum = mix64(r0);
-          if (lane == 0) L.kG[0] = r0;
+          if (lane == 0) kG[0] = r0;
           if (EXCL) {
             const uint32_t r1 = readlane32(a.sub.r1[s], 0);
             zsum += mix64(r1);
-            if (lane == 0) L.kG[1] = r1;
+            if (lane == 0) kG[1] = r1;
           }
           expand = true;
         } else {
           const uint32_t klen = (uint32_t)readlane64(rec[R_KLEN], 0);
           for (uint32_t k = lane; k < F; k += kWave) fr[k] = rec[R_HDR + k];
-          for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = ((const uint32_t*)(rec + R_HDR + F))[j];
+          for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + R_HDR + F))[j];
           __threadfence_block();
           if (lane < (int)wp) {
             rP = fr[lane];
@@ -832,6 +850,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
       }
       WideCtx wctx;
       wctx.stk = stk;
+      wctx.kG = kG;
       wctx.F = F;
       wctx.wp = wp;
       wctx.base = base;
@@ -852,7 +871,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
               xe = ballot(nz) == 0;
             }
-            if (xe) emit(a, acc, zsum, kroot + d, L.kG);
+            if (xe) emit(a, acc, zsum, kroot + d, kG);
             do_pop = true;
           } else {
             if (lane < (int)wp) L.sP[lane] = rP;
@@ -862,7 +881,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
             // One pass over the rows of P u X: t_u for the pivot and, when
             // |cand| <= 64, the fini vertices with a neighbour in cand (the
             // vertices a re-based node keeps; give up beyond 64).
-            bool ok = p_cnt <= 64 && kroot + d + kCFrames <= kKMax;
+            bool ok = p_cnt <= 64 && kroot + d + kCFrames <= kcap;
             uint32_t nx = 0;
             uint64_t best = 0;
             uint32_t bu = 0;
@@ -966,7 +985,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
                 const uint32_t gX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
                 const uint64_t Fc = EXCL ? readlane64(cF, 0) : 0;
                 wctx.top = d;
-                const bool handed = a.hand && kroot + d <= kHandK && hand_off<EXCL>(a, L, c, gX, s, Fc, zsum, kroot + d);
+                const bool handed = a.hand && kroot + d <= kHandK && hand_off<EXCL>(a, kG, c, gX, s, Fc, zsum, kroot + d);
                 if (handed) {
                   // a handed-off subtree is work done here as far as donation
                   // pacing goes, else the wide frames would rarely be offered
@@ -978,8 +997,12 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
                   const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
                   const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
                   dg.t_rebase += now() - tr;
-                  compact_dfs<EXCL>(a, L, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc, can_donate,
-                                    since, &wctx, dg);
+                  if (bigk)
+                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                                            can_donate, since, &wctx, dg);
+                  else
+                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                                             can_donate, since, &wctx, dg);
                 }
                 rebased = true;
                 do_pop = true;
@@ -995,7 +1018,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               acc.ssum += s_mem;
               acc.esum += n_ext;
               if (ksplit > 1 && !cont && d == 0)
-                rExt = split_root<EXCL>(a, L, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
+                rExt = split_root<EXCL>(a, kG, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
             }
             __syncthreads();
           }
@@ -1017,7 +1040,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               rXp |= qb;
               continue;
             }
-            if (d + 2 > cap || kroot + d + 1 >= kKMax) {
+            if (d + 2 > cap || kroot + d + 1 >= kcap) {
               overflow = true;
               break;
             }
@@ -1038,7 +1061,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
             const uint32_t gq = gid[q];
             if (lane == 0) {
               fr[O_Z] = zsum;
-              L.kG[kroot + d] = gq;
+              kG[kroot + d] = gq;
             }
             zsum += mix64(gq);
             if (lane == 0) ch[O_Z] = zsum;
@@ -1142,7 +1165,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
       // a donation among the compact kernel's own waves
       const uint64_t* rec = a.pool + idx * kBlockWords;
       s = (uint32_t)readlane64(rec[R_S], 0);
-      compact_from_record<EXCL>(rec, c, L, P, Xp, Xx, ext, zsum, F, klen);
+      compact_from_record<EXCL>(rec, c, L.kG, P, Xp, Xx, ext, zsum, F, klen);
       __threadfence_block();
       if (lane == 0) pool_push(a, (uint32_t)idx);
     } else {
@@ -1153,8 +1176,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;
-    compact_dfs<EXCL>(a, L, c, s, P, Xp, Xx, ext, F, zsum, !pooled, klen, wv, acc, can_donate, since,
-                      (const WideCtx*)nullptr, dg);
+    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, F, zsum, !pooled, klen, wv, acc, can_donate,
+                             since, (const WideCtx*)nullptr, dg);
     if (lane == 0) {
       if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
       if (a.count_v && acc.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)acc.tc);

@@ -36,7 +36,7 @@ struct imce_state {
   mce_opts opts;
   DevBuf bsrc, bdst, keys, idx, keys2, idx2, keep, pos, eu, ev, hkeys, hidx, hkeys2, hidx2, dkeys, didx, dkeys2, didx2,
       addcnt, degw, p, x, words, gwords, off, goff, stats, arena, gids, order, bad, new_off, new_vert, cand_off,
-      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, sdefer, del_off, del_vert;
+      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, sdefer, sbig, del_off, del_vert;
   uint64_t cap_nc = 0, cap_nv = 0, cap_cc = 0, cap_cv = 0;
   EnumWork ew;
   void* scan_tmp = nullptr;
@@ -49,7 +49,9 @@ namespace {
 
 inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
 
-constexpr uint32_t kSubMaxK = 64;     // largest new clique the subsumed kernel takes
+constexpr uint32_t kSubMaxK = 64;     // largest new clique the bitmask subsumed kernel takes
+constexpr uint32_t kBigK = kMaxCand + 2;  // largest new clique of any edge subproblem (|K| = 2 + |cand|)
+constexpr uint32_t kBigInvolved = 64;     // batch-edge endpoints inside one large new clique
 constexpr uint32_t kSubMaxS = 1024;   // candidate subsets per new clique
 constexpr uint32_t kSubMaxPairs = 256;
 constexpr uint32_t kEdgeRowsPerWave = 16;
@@ -284,14 +286,15 @@ struct SubLds {
 // Subsumed-clique candidates of the new cliques (or of those listed in
 // `list`, `*nlist` of them).  A clique whose batch edges or subsets exceed
 // this instance's LDS capacities is appended to `defer` (when given) for the
-// large-capacity instance; without `defer` that is an error (flag 2).
+// large-capacity instance; without `defer` that is an error (flag 2).  A
+// clique of more than kSubMaxK vertices goes to `big` for k_subsumed_big.
 // sctl: [0] packed candidate counter (cands << 32 | verts), [1] flags
 // (1: clique too large, 2: too many subsets or pairs, 4: candidate overflow),
-// [2] deferred cliques
+// [2] deferred cliques, [3] cliques for k_subsumed_big
 template <uint32_t MAXS, uint32_t MAXP>
 __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* __restrict__ list,
                                                  const uint64_t* __restrict__ nlist, uint32_t* defer,
-                                                 const uint64_t* __restrict__ noff,
+                                                 uint32_t* big, const uint64_t* __restrict__ noff,
                                                  const uint32_t* __restrict__ nvert, uint64_t n,
                                                  const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
                                                  const uint64_t* __restrict__ hkeys, uint64_t nh,
@@ -306,7 +309,12 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
     const uint64_t b0 = noff[ci];
     const uint32_t k = (uint32_t)(noff[ci + 1] - b0);
     if (k > kSubMaxK) {
-      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 1ULL);
+      if (lane == 0) {
+        if (big)
+          big[atomicAdd((unsigned long long*)&sctl[3], 1ULL)] = (uint32_t)ci;
+        else
+          atomicOr((unsigned long long*)&sctl[1], 1ULL);
+      }
       continue;
     }
     if (lane < (int)k) L.c[lane] = nvert[b0 + lane];
@@ -437,6 +445,213 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
       const uint64_t below = mem ? __popcll(sm & ((1ULL << lane) - 1)) : 0;
       if (mem) cand_vert[pos + below] = x;
       const uint64_t z = wave_sum_u64(mem ? mix64(x) : 0);
+      if (lane == 0) {
+        cand_off[id] = pos;
+        cand_hash[id] = clique_term(z, kk);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Subsumed-clique candidates of new cliques with more than kSubMaxK vertices
+// (Algorithm 7 as in k_subsumed).  Only the endpoints of batch edges inside c
+// can leave a subset, so subsets are bitmasks over those "involved" vertices
+// (at most kBigInvolved of them); every other vertex of c belongs to every
+// subset.  One wave per listed clique.  Flags as in k_subsumed (2: more than
+// kBigInvolved involved vertices, kSubMaxPairs batch edges or kSubMaxS subsets).
+struct BigLds {
+  uint32_t c[kBigK];
+  uint16_t invof[kBigK];  // involved index of each position of c, or 0xFFFF
+  uint32_t ipos[kBigInvolved];
+  uint64_t pairs[kSubMaxPairs];  // batch edges inside c as (position, position), then as involved-index masks
+  uint64_t S[2][kSubMaxS];
+  uint32_t np, ni, bad;
+};
+
+__global__ void __launch_bounds__(64) k_subsumed_big(const uint32_t* __restrict__ list, const uint64_t* __restrict__ nlist,
+                                                     const uint64_t* __restrict__ noff,
+                                                     const uint32_t* __restrict__ nvert, uint64_t n,
+                                                     const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                                                     const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* sctl,
+                                                     uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
+                                                     uint64_t cap_c, uint64_t cap_v) {
+  __shared__ BigLds L;
+  const int lane = threadIdx.x;
+  const uint64_t items = *nlist;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const uint64_t ci = list[it];
+    const uint64_t b0 = noff[ci];
+    const uint32_t k = (uint32_t)(noff[ci + 1] - b0);
+    if (k > kBigK) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 1ULL);
+      continue;
+    }
+    for (uint32_t j = lane; j < k; j += kWave) {
+      L.c[j] = nvert[b0 + j];
+      L.invof[j] = 0xFFFF;
+    }
+    if (lane == 0) {
+      L.np = 0;
+      L.ni = 0;
+      L.bad = 0;
+    }
+    __syncthreads();
+    // batch edges inside c (each pair once, from its smaller vertex)
+    for (uint32_t j = lane; j < k; j += kWave) {
+      const uint32_t x = L.c[j];
+      const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)x * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(x + 1) * n);
+      for (uint64_t t = lo; t < hi; ++t) {
+        const uint32_t w = (uint32_t)(dkeys[t] % n);
+        if (w <= x) continue;
+        const int64_t j2 = bsearch_u32(L.c, k, w);
+        if (j2 >= 0) {
+          const uint32_t slot = atomicAdd(&L.np, 1u);
+          if (slot < kSubMaxPairs) L.pairs[slot] = (uint64_t)j | ((uint64_t)j2 << 32);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t npairs = L.np;
+    if (npairs > kSubMaxPairs) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      __syncthreads();
+      continue;
+    }
+    // involved vertices: the distinct endpoints, numbered in order of appearance
+    if (lane == 0) {
+      for (uint32_t e = 0; e < npairs && !L.bad; ++e) {
+        const uint32_t ends[2] = {(uint32_t)L.pairs[e], (uint32_t)(L.pairs[e] >> 32)};
+        uint64_t m = 0;
+        for (uint32_t z = 0; z < 2; ++z) {
+          uint32_t ix = L.invof[ends[z]];
+          if (ix == 0xFFFF) {
+            if (L.ni >= kBigInvolved) {
+              L.bad = 1;
+              break;
+            }
+            ix = L.ni++;
+            L.invof[ends[z]] = (uint16_t)ix;
+            L.ipos[ix] = ends[z];
+          }
+          m |= 1ULL << ix;
+        }
+        L.pairs[e] = m;
+      }
+    }
+    __syncthreads();
+    if (L.bad) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t ni = L.ni;
+    // Algorithm 7: split every subset that holds both ends of a batch edge
+    int cur = 0;
+    uint32_t ns = 1;
+    if (lane == 0) L.S[0][0] = ni == 64 ? ~0ULL : ((1ULL << ni) - 1);
+    bool overflow = false;
+    for (uint32_t e = 0; e < npairs && !overflow; ++e) {
+      __syncthreads();
+      const uint64_t pm = L.pairs[e];
+      const uint64_t bx = pm & (~pm + 1), by = pm & ~bx;
+      uint32_t nout = 0;
+      for (uint32_t base = 0; base < ns; base += kWave) {
+        const uint32_t i = base + lane;
+        const uint64_t sm = i < ns ? L.S[cur][i] : 0;
+        const bool split = i < ns && (sm & pm) == pm;
+        const bool keep1 = i < ns && !split;
+        const uint32_t cnt = split ? 2u : (keep1 ? 1u : 0u);
+        const uint32_t incl = wave_incl_scan_u32(cnt);
+        const uint32_t total = readlane32(incl, 63);
+        if (nout + total > kSubMaxS) {
+          overflow = true;
+          break;
+        }
+        const uint32_t o = nout + incl - cnt;
+        if (split) {
+          L.S[cur ^ 1][o] = sm & ~bx;
+          L.S[cur ^ 1][o + 1] = sm & ~by;
+        } else if (keep1) {
+          L.S[cur ^ 1][o] = sm;
+        }
+        nout += total;
+      }
+      cur ^= 1;
+      ns = nout;
+    }
+    __syncthreads();
+    if (overflow) {
+      if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 2ULL);
+      continue;
+    }
+    for (uint32_t i = 0; i < ns; ++i) {
+      const uint64_t sm = L.S[cur][i];
+      bool dup = false;
+      for (uint32_t j = lane; j < i && !dup; j += kWave) dup = L.S[cur][j] == sm;
+      if (ballot(dup)) continue;
+      // position j of c is in c' unless it is an involved vertex left out
+      auto member = [&](uint32_t j) {
+        const uint32_t ix = L.invof[j];
+        return ix == 0xFFFF || ((sm >> ix) & 1ULL);
+      };
+      // the member of c' with the smallest degree in G
+      uint64_t mn = ~0ULL;
+      for (uint32_t j = lane; j < k; j += kWave) {
+        if (!member(j)) continue;
+        const uint32_t x = L.c[j];
+        const uint64_t key = ((rp[x + 1] - rp[x]) << 13) | j;
+        mn = key < mn ? key : mn;
+      }
+      for (int o = 32; o >= 1; o >>= 1) {
+        uint64_t t = __shfl_xor(mn, o, kWave);
+        mn = t < mn ? t : mn;
+      }
+      const uint32_t la = (uint32_t)(mn & 8191);
+      const uint32_t a = L.c[la];
+      // is some w outside c' adjacent in G to every vertex of c'?
+      bool extends = false;
+      const uint64_t ab = rp[a], ae = rp[a + 1];
+      for (uint64_t j0 = ab; j0 < ae && !extends; j0 += kWave) {
+        const uint64_t j = j0 + lane;
+        bool ok = j < ae;
+        const uint32_t w = ok ? col[j] : 0;
+        if (ok) {
+          const int64_t pos = bsearch_u32(L.c, k, w);
+          if (pos >= 0 && member((uint32_t)pos)) ok = false;
+        }
+        for (uint32_t y = 0; ok && y < k; ++y) {
+          if (y == la || !member(y)) continue;
+          const uint32_t yy = L.c[y];
+          ok = bsearch_u32(col + rp[yy], rp[yy + 1] - rp[yy], w) >= 0;
+        }
+        extends = ballot(ok) != 0;
+      }
+      if (extends) continue;
+      // c' is a maximal clique of G: a subsumed-clique candidate
+      const uint32_t kk = k - (ni - (uint32_t)__popcll(sm));
+      uint64_t old = 0;
+      if (lane == 0) old = atomicAdd((unsigned long long*)&sctl[0], (unsigned long long)((1ULL << 32) | kk));
+      old = readlane64(old, 0);
+      const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+      if (id >= cap_c || pos + kk > cap_v) {
+        if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 4ULL);
+        continue;
+      }
+      uint64_t z = 0;
+      uint32_t written = 0;
+      for (uint32_t j0 = 0; j0 < k; j0 += kWave) {
+        const uint32_t j = j0 + lane;
+        const bool mem = j < k && member(j);
+        const uint64_t bm = ballot(mem);
+        if (mem) {
+          const uint32_t x = L.c[j];
+          cand_vert[pos + written + mask_prefix(bm, lane)] = x;
+          z += mix64(x);
+        }
+        written += (uint32_t)__popcll(bm);
+      }
+      z = wave_sum_u64(z);
       if (lane == 0) {
         cand_off[id] = pos;
         cand_hash[id] = clique_term(z, kk);
@@ -740,13 +955,14 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
     st->cap_cc = 1 << 20;
     st->cap_cv = 1 << 24;
   }
-  uint64_t sctl[2];
+  uint64_t sctl[4];
   for (int attempt = 0;; ++attempt) {
     MCE_TRY(st->cand_off.ensure((st->cap_cc + 1) * 8));
     MCE_TRY(st->cand_vert.ensure(st->cap_cv * 4));
     MCE_TRY(st->cand_hash.ensure(st->cap_cc * 8));
     MCE_TRY(st->sctl.ensure(4 * 8));
     MCE_TRY(st->sdefer.ensure(std::max<uint64_t>(nc_new, 1) * 4));
+    MCE_TRY(st->sbig.ensure(std::max<uint64_t>(nc_new, 1) * 4));
     MCE_TRY_HIP(hipMemsetAsync(st->sctl.p, 0, 32, s));
     if (nc_new) {
       // most new cliques hold one or two batch edges: a small-LDS pass with
@@ -754,21 +970,29 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
       const uint32_t grid = (uint32_t)std::min<uint64_t>(nc_new, 32768);
       uint64_t* sc = st->sctl.as<uint64_t>();
       uint32_t* defer = st->sdefer.as<uint32_t>();
+      uint32_t* big = st->sbig.as<uint32_t>();
       hipLaunchKernelGGL((k_subsumed<kSubFastS, kSubFastPairs>), dim3(grid), dim3(64), 0, s, nc_new, nullptr, nullptr,
-                         defer, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd, sc,
-                         st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(),
-                         st->cap_cc, st->cap_cv);
+                         defer, big, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk,
+                         nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
+                         st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       hipLaunchKernelGGL((k_subsumed<kSubMaxS, kSubMaxPairs>), dim3(1024), dim3(64), 0, s, nc_new, defer, sc + 2,
-                         nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk, nd,
-                         sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(),
-                         st->cap_cc, st->cap_cv);
+                         nullptr, nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m,
+                         dk, nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
+                         st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
+      MCE_TRY_HIP(hipGetLastError());
+      // new cliques above kSubMaxK vertices (rare: a batch edge inside a very large clique)
+      hipLaunchKernelGGL(k_subsumed_big, dim3(256), dim3(64), 0, s, big, sc + 3, st->new_off.as<uint64_t>(),
+                         st->new_vert.as<uint32_t>(), n, rp, col, dk, nd, sc, st->cand_off.as<uint64_t>(),
+                         st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
     }
     MCE_TRY_HIP(hipMemcpyAsync(sctl, st->sctl.p, 16, hipMemcpyDeviceToHost, s));
     MCE_TRY_HIP(hipStreamSynchronize(s));
     if (sctl[1] & 3ULL) {
-      set_error("a new clique exceeds %u vertices or splits into more than %u subsets", kSubMaxK, kSubMaxS);
+      set_error("a new clique holds more than %u batch edges, more than %u of its vertices are ends of batch "
+                "edges (cliques above %u vertices), or it splits into more than %u subsets",
+                kSubMaxPairs, kBigInvolved, kSubMaxK, kSubMaxS);
       return MCE_ENOTSUP;
     }
     if (!(sctl[1] & 4ULL)) break;
@@ -862,7 +1086,7 @@ void release_state(imce_state* st) {
                     &st->degw, &st->p, &st->x, &st->words, &st->gwords, &st->off, &st->goff, &st->stats,
                     &st->arena, &st->gids, &st->order, &st->bad, &st->new_off, &st->new_vert, &st->cand_off,
                     &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq,
-                    &st->sctl, &st->sdefer,
+                    &st->sctl, &st->sdefer, &st->sbig,
                     &st->del_off, &st->del_vert};
   for (DevBuf* b : bufs) b->release();
   st->ew.release();

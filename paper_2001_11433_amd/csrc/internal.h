@@ -31,6 +31,13 @@ void set_error(const char* fmt, ...);
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxCand = 4096;  // |cand| per subproblem: 64 words of 64 bits
 constexpr uint32_t kBlockWords = 1024;  // one donated-task record
+// K list of a search wave in LDS: enough for subproblems whose cliques stay
+// below 512 vertices.
+constexpr uint32_t kKLds = 512;
+// K list capacity of a search wave when a subproblem's cliques can reach 512
+// vertices (its LDS list is shorter): any clique within the envelope
+// (|K| <= 2 + kMaxCand) plus the compact search's depth margin.
+constexpr uint32_t kKBig = kMaxCand + 72;
 
 // Control block of one enumeration launch (uint64 words).
 enum {
@@ -93,6 +100,8 @@ struct EnumArgs {
   uint32_t* hand_idx;    // record index -> first unit
   uint64_t hand_cap;     // records (at most 2^26, so the packed request counter cannot carry into
                          // a record that passes both checks)
+  uint32_t* kbig;        // per-wave K lists of kKBig entries (gridDim.x of them), for subproblems with
+                         // |cand| + |K at the root| + 2 > 512; null when no subproblem needs them
 };
 
 // A node is handed off only when its K list has at most kHandK vertices.
@@ -136,11 +145,12 @@ struct DevBuf {
 // pool, DFS stacks).  Each incremental state owns one, so sessions on
 // different streams never share them.
 struct EnumWork {
-  DevBuf queue, ctl, pool, pool_next, stacks, hand, hand_idx, hkeys, hkeys2, hvals, hvals2;
+  DevBuf queue, ctl, pool, pool_next, stacks, hand, hand_idx, hkeys, hkeys2, hvals, hvals2, kbig;
   void* sort_tmp = nullptr;
   size_t sort_bytes = 0;
   void release() {
-    for (DevBuf* b : {&queue, &ctl, &pool, &pool_next, &stacks, &hand, &hand_idx, &hkeys, &hkeys2, &hvals, &hvals2})
+    for (DevBuf* b : {&queue, &ctl, &pool, &pool_next, &stacks, &hand, &hand_idx, &hkeys, &hkeys2, &hvals, &hvals2,
+                      &kbig})
       b->release();
     if (sort_tmp) (void)hipFree(sort_tmp);
     sort_tmp = nullptr;

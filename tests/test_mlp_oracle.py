@@ -70,3 +70,32 @@ def test_bfloat16_round_to_nearest_even():
 def test_spearman():
     assert abs(mlp.spearman(np.arange(10), np.arange(10) ** 3) - 1) < 1e-12
     assert abs(mlp.spearman(np.arange(10), -np.arange(10)) + 1) < 1e-12
+
+
+def test_forward_bf16_by_hand():
+    # One live path, with a value chosen to round at each of the points where
+    # the BF16 inference rounds (weights, standardised input, each hidden
+    # activation; mu and sigma stay FP32; the output accumulates exactly).
+    d = {k: np.zeros(s) if s else 0.0 for k, (o, s) in mlp.OFFSETS.items()}
+    d["mu"] = np.array([0.5, 0, 0, 0])
+    d["sigma"] = np.array([0.5, 1, 1, 1])
+    d["W1"][0, 0] = 1 + 2 ** -8          # bf16: a tie, rounds to even -> 1.0
+    d["W2"][0, 0] = 1 + 2 ** -7          # exact in bf16
+    d["w3"][0] = 2.0
+    d["b3"] = 0.5
+    p = mlp.pack(d)
+    # x = 1.005859375: (x - 0.5) / 0.5 = 1.01171875 = 1 + 3*2^-8 -> bf16 rounds up to 1 + 2^-6
+    x = np.array([[1.005859375, 0, 0, 0]])
+    xs = 1 + 2 ** -6
+    h1 = 1.0 * xs                         # 1.015625, exact in bf16
+    a2 = (1 + 2 ** -7) * h1               # 1.0235595703125 -> bf16 1.0234375 (spacing 2^-7)
+    h2 = 1.0234375
+    assert a2 == 1.0235595703125
+    want = 2.0 * h2 + 0.5                 # 2.546875
+    assert mlp.forward_bf16(p, x)[0] == want == 2.546875
+    # the FP32/FP64 path keeps every digit and so differs
+    exact = 2.0 * ((1 + 2 ** -7) * ((1 + 2 ** -8) * 1.01171875)) + 0.5
+    assert abs(mlp.forward(p, x)[0] - exact) < 1e-12 and mlp.forward(p, x)[0] != want
+    # a negative pre-activation is cut by the ReLU before rounding
+    x2 = np.array([[0.25, 0, 0, 0]])      # xs = -0.5 -> h1 = 0 -> y = b3
+    assert mlp.forward_bf16(p, x2)[0] == 0.5

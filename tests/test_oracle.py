@@ -38,6 +38,43 @@ def test_mix64_matches_published_splitmix64_outputs():
     assert [O.mix64((1234567 + i * G) & M) for i in range(5)] == want
 
 
+def _splitmix64_finaliser(x):
+    # splitmix64's output step, written from its published definition (add the
+    # golden gamma, then xor-shift 30 / multiply / xor-shift 27 / multiply /
+    # xor-shift 31), independent of the oracle's code
+    M = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def test_clique_hash_composition_by_hand():
+    # hc(c) = mix(sum_{v in c} mix(v) + |c| * G) mod 2^64 (the set hash's
+    # per-clique term).  The Python finaliser is first tied to the published
+    # splitmix64 outputs, then composed by hand for an empty set, a singleton
+    # and a triangle; literal values guard the composition itself.
+    G = 0x9E3779B97F4A7C15
+    M = (1 << 64) - 1
+    f = _splitmix64_finaliser
+    assert f(0) == 0xE220A8397B1DCDAF
+    assert [f((1234567 + i * G) & M) for i in range(3)] == [6457827717110365317, 3203168211198807973,
+                                                           9817491932198370423]
+    # empty set: no vertex terms and |c| = 0, so hc is the generator's first output from seed 0
+    assert O.lib().orc_clique_hash(None, 0) == 0xE220A8397B1DCDAF
+    single = f((f(1234567) + G) & M)
+    assert single == f((6457827717110365317 + G) & M)
+    assert O.clique_hash([1234567]) == single
+    tri = f((f(1) + f(2) + f(3) + 3 * G) & M)
+    assert O.clique_hash([3, 1, 2]) == tri
+    assert (single, tri) == (0xB49A95E7EB5B2DB7, 0x0770BF84CF6243D9)
+    # each part of the composition matters: without the size term, without the
+    # outer mix, or with XOR instead of the sum the values differ
+    assert O.clique_hash([1, 2, 3]) != f((f(1) + f(2) + f(3)) & M)
+    assert O.clique_hash([1, 2, 3]) != (f(1) + f(2) + f(3) + 3 * G) & M
+    assert O.clique_hash([1, 2, 3]) != f((f(1) ^ f(2) ^ f(3)) + 3 * G & M)
+
+
 def test_clique_hash_is_order_free_and_separates_small_families():
     assert O.clique_hash([3, 1, 2]) == O.clique_hash([1, 2, 3])
     seen = {}
@@ -410,3 +447,53 @@ def test_imce_random_streams_equal_recompute_and_diff():
             c2, h2, _ = O.mce_root(nxt)
             assert (c, h) == (c2, h2)
             cur = nxt
+
+
+# --------------------------------------------------------------------------
+# CSR validity (the input contract of Section 3: simple undirected graphs)
+
+def _raw(n, row_ptr, col):
+    return gg.Graph(n, np.asarray(row_ptr, np.uint64), np.asarray(col, np.uint32))
+
+
+def test_csr_validity_rejects_each_malformation():
+    ok = gg.from_edge_list(4, [(0, 1), (1, 2), (2, 3), (0, 3)])
+    assert O.csr_valid(ok)
+    assert O.csr_valid(gg.edgeless(5))
+    # path 0-1-2 written out by hand: row_ptr [0,1,3,4], col [1, 0,2, 1]
+    assert O.csr_valid(_raw(3, [0, 1, 3, 4], [1, 0, 2, 1]))
+    assert not O.csr_valid(_raw(3, [1, 2, 4, 5], [1, 0, 2, 1]))      # row_ptr[0] != 0 (shifted)
+    assert not O.csr_valid(_raw(3, [0, 2, 1, 4], [1, 0, 2, 1]))      # row_ptr decreasing
+    assert not O.csr_valid(_raw(3, [0, 1, 3, 4], [1, 2, 0, 1]))      # row 1 unsorted
+    assert not O.csr_valid(_raw(3, [0, 1, 3, 4], [1, 0, 0, 1]))      # repeated entry in row 1
+    assert not O.csr_valid(_raw(3, [0, 1, 3, 4], [1, 0, 1, 1]))      # self-loop 1-1
+    assert not O.csr_valid(_raw(3, [0, 1, 3, 4], [1, 0, 7, 1]))      # id >= n
+    assert not O.csr_valid(_raw(3, [0, 1, 2, 3], [1, 0, 1]))         # 1-2 stored on one side only
+    assert not O.csr_valid(_raw(3, [0, 1, 3, 3], [1, 0, 2]))         # 1-2 stored on one side only
+
+
+# --------------------------------------------------------------------------
+# clique-size distribution (the per-graph histogram of Section 6.1)
+
+def test_size_histogram_closed_forms_and_brute_force():
+    def hist(r):
+        return {k: int(c) for k, c in enumerate(r.sizes) if c}
+    assert hist(O.mce_parmce(gg.complete(9))) == {9: 1}
+    assert hist(O.mce_parmce(gg.edgeless(6))) == {1: 6}
+    assert hist(O.mce_parmce(gg.cycle(7))) == {2: 7}
+    # Moon-Moser n = 3k: 3^k cliques of size k (one vertex per part)
+    assert hist(O.mce_parmce(gg.moon_moser(12))) == {4: 81}
+    # complete multipartite: every transversal, of size = number of parts
+    assert hist(O.mce_parmce(gg.complete_multipartite([2, 3, 1]))) == {3: 6}
+    rng = np.random.default_rng(5)
+    for t in range(30):
+        n = int(rng.integers(1, 14))
+        g = gg.er(n, float(rng.random()), seed=500 + t)
+        _, _, cl = O.mce_brute(g, cliques=True)
+        want = {}
+        for c in cl:
+            want[len(c)] = want.get(len(c), 0) + 1
+        for rank in RANKS:
+            r = O.mce_parmce(g, rank)
+            assert hist(r) == want
+            assert int(r.sizes.sum()) == r.count
