@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "Graph", "csr_from_edges", "edges_of", "er", "rmat", "chung_lu",
     "plant_communities", "complete", "edgeless", "cycle", "complete_multipartite",
-    "moon_moser", "disjoint_union", "from_edge_list", "edge_stream", "add_edges",
+    "moon_moser", "disjoint_union", "from_edge_list", "edge_stream", "add_edges", "remove_edges", "deletion_stream",
     "relabel", "star", "path",
 ]
 
@@ -278,6 +278,51 @@ def add_edges(g: Graph, src: np.ndarray, dst: np.ndarray) -> Graph:
     u, v = edges_of(g)
     return csr_from_edges(g.n, np.concatenate([u, np.asarray(src, np.int64)]),
                           np.concatenate([v, np.asarray(dst, np.int64)]), dict(g.meta))
+
+
+def remove_edges(g: Graph, src: np.ndarray, dst: np.ndarray) -> Graph:
+    """g without the listed pairs (in either orientation); pairs that are not
+    edges are ignored."""
+    u, v = edges_of(g)
+    a = np.minimum(np.asarray(src, np.int64), np.asarray(dst, np.int64))
+    b = np.maximum(np.asarray(src, np.int64), np.asarray(dst, np.int64))
+    gone = np.isin(u * np.int64(g.n) + v, a * np.int64(g.n) + b)
+    return csr_from_edges(g.n, u[~gone], v[~gone], dict(g.meta))
+
+
+def deletion_stream(g: Graph, batches: int, rho_min: int, rho_max: int, seed: int = 3,
+                    junk_fraction: float = 0.0) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Pre-generates batches of edge deletions from `g`: each batch draws
+    U{rho_min..rho_max} distinct edges of the current graph uniformly (the
+    graph shrinks batch by batch); a `junk_fraction` share of extra pairs are
+    repeats or non-edges, which a deletion step must skip.  Returns
+    [(src uint32[rho], dst uint32[rho])]."""
+    rng = _rng(seed)
+    u, v = edges_of(g)
+    alive = np.ones(u.size, bool)
+    out: List[Tuple[np.ndarray, np.ndarray]] = []
+    for _ in range(batches):
+        idx = np.flatnonzero(alive)
+        rho = min(int(rng.integers(rho_min, rho_max + 1)), idx.size)
+        pick = rng.choice(idx, rho, replace=False) if rho else np.zeros(0, np.int64)
+        alive[pick] = False
+        s, d = u[pick].copy(), v[pick].copy()
+        flip = rng.random(rho) < 0.5
+        s[flip], d[flip] = d[flip].copy(), s[flip].copy()
+        nj = int(round(rho * junk_fraction))
+        if nj and g.n > 1:
+            js = rng.integers(0, g.n, nj)
+            jd = (js + rng.integers(1, g.n, nj)) % g.n
+            rep = rng.integers(0, max(rho, 1), nj)
+            use_rep = (rng.random(nj) < 0.5) & (rho > 0)
+            js = np.where(use_rep, s[rep % max(rho, 1)] if rho else js, js)
+            jd = np.where(use_rep, d[rep % max(rho, 1)] if rho else jd, jd)
+            s = np.concatenate([s, js])
+            d = np.concatenate([d, jd])
+            perm = rng.permutation(s.size)
+            s, d = s[perm], d[perm]
+        out.append((s.astype(np.uint32), d.astype(np.uint32)))
+    return out
 
 
 # ----------------------------------------------------------------------------

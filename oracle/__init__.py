@@ -82,6 +82,8 @@ def lib():
         L.orc_imce_snapshot.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Result), ctypes.POINTER(_Cliques)]
         L.orc_imce_add.argtypes = [ctypes.c_void_p, P32, P32, ctypes.c_uint64, ctypes.POINTER(_ImceResult),
                                    ctypes.POINTER(_Cliques), ctypes.POINTER(_Cliques), ctypes.c_int]
+        L.orc_imce_remove.argtypes = [ctypes.c_void_p, P32, P32, ctypes.c_uint64, ctypes.POINTER(_ImceResult),
+                                      ctypes.POINTER(_Cliques), ctypes.POINTER(_Cliques)]
         _lib = L
     return _lib
 
@@ -219,6 +221,17 @@ class Imce:
 
     def add(self, src, dst, cliques: bool = False, check_form: bool = False):
         """Returns a dict of the batch result (and 'new'/'del' clique lists)."""
+        return self._update(lambda s, d, rho, r, cn, cd: lib().orc_imce_add(self._h, s, d, rho, r, cn, cd,
+                                                                           int(check_form)), src, dst, cliques)
+
+    def remove(self, src, dst, cliques: bool = False):
+        """Edge deletions by the reduction of Section 5.3.  Same dict as add:
+        'new' are the cliques that become maximal, 'del' those that stop
+        being maximal."""
+        return self._update(lambda s, d, rho, r, cn, cd: lib().orc_imce_remove(self._h, s, d, rho, r, cn, cd),
+                            src, dst, cliques)
+
+    def _update(self, call, src, dst, cliques):
         s = np.ascontiguousarray(src, dtype=np.uint32)
         d = np.ascontiguousarray(dst, dtype=np.uint32)
         if s.size == 0:
@@ -239,19 +252,18 @@ class Imce:
                 vert_d = np.zeros(cap_v, np.uint32)
                 cn = _Cliques(cap_c, cap_v, _p64(off_n), _p32(vert_n), 0, 0)
                 cd = _Cliques(cap_c, cap_v, _p64(off_d), _p32(vert_d), 0, 0)
-                rc = lib().orc_imce_add(self._h, _p32(s), _p32(d), rho, ctypes.byref(r), ctypes.byref(cn),
-                                        ctypes.byref(cd), int(check_form))
+                rc = call(_p32(s), _p32(d), rho, ctypes.byref(r), ctypes.byref(cn), ctypes.byref(cd))
                 if rc != 0:
-                    raise ValueError("oracle imce_add failed: %d" % rc)
+                    raise ValueError("oracle incremental update failed: %d" % rc)
                 if cn.n_cliques <= cap_c and cn.n_verts <= cap_v and cd.n_cliques <= cap_c and cd.n_verts <= cap_v:
                     break
                 raise RuntimeError("clique lists exceed the oracle's list capacity")
             new = [tuple(int(x) for x in vert_n[off_n[i]:off_n[i + 1]]) for i in range(int(cn.n_cliques))]
             dele = [tuple(int(x) for x in vert_d[off_d[i]:off_d[i + 1]]) for i in range(int(cd.n_cliques))]
         else:
-            rc = lib().orc_imce_add(self._h, _p32(s), _p32(d), rho, ctypes.byref(r), None, None, int(check_form))
+            rc = call(_p32(s), _p32(d), rho, ctypes.byref(r), None, None)
             if rc != 0:
-                raise ValueError("oracle imce_add failed: %d" % rc)
+                raise ValueError("oracle incremental update failed: %d" % rc)
             new = dele = None
         out = {k: int(getattr(r, k)) for k, _ in _ImceResult._fields_}
         if cliques:

@@ -380,6 +380,43 @@ bool csr_ok(uint64_t n, const uint64_t* rp, const uint32_t* col) {
   return true;
 }
 
+bool maximal_in(const Adj& G, const VSet& c) {
+  if (c.empty()) return false;
+  for (uint32_t w : G.rows[c[0]]) {
+    if (contains(c, w)) continue;
+    bool all = true;
+    for (uint32_t y : c) if (!G.has(w, y)) { all = false; break; }
+    if (all) return false;
+  }
+  return true;
+}
+
+// Algorithm 7's splitting: the subsets of c that keep no edge of the batch,
+// obtained by splitting, for each batch edge (x, y) inside c, every subset
+// holding both ends into one without x and one without y.
+std::set<VSet> edge_free_subsets(const VSet& c, const std::map<std::pair<uint32_t, uint32_t>, uint64_t>& index) {
+  std::set<VSet> S{c};
+  for (size_t x = 0; x < c.size(); ++x)
+    for (size_t y = x + 1; y < c.size(); ++y) {
+      auto key = std::make_pair(c[x], c[y]);
+      if (!index.count(key)) continue;
+      std::set<VSet> S2;
+      for (const VSet& cp : S) {
+        if (contains(cp, key.first) && contains(cp, key.second)) {
+          VSet c1 = cp, c2 = cp;
+          erase_sorted(c1, key.first);
+          erase_sorted(c2, key.second);
+          S2.insert(std::move(c1));
+          S2.insert(std::move(c2));
+        } else {
+          S2.insert(cp);
+        }
+      }
+      S.swap(S2);
+    }
+  return S;
+}
+
 // ---------------------------------------------------------------------------
 // IMCE state: the graph G and the set C of its maximal cliques (Section 5).
 struct ImceState {
@@ -679,6 +716,87 @@ int orc_imce_add(void* h, const uint32_t* src, const uint32_t* dst, uint64_t rho
   if (del_out) {
     std::vector<VSet> v(del.begin(), del.end());
     write_cliques(v, del_out);
+  }
+  return 0;
+}
+
+// Decremental step (Section 5.3): deleting a batch H from G reduces to the
+// incremental case on G' = G - H with the same batch, because G = G' + H:
+//  * C(G) \ C(G') = Lambda_new(G', H), the maximal cliques of G that hold an
+//    edge of H: Algorithm 5 with the exclusion of Algorithm 8, run on G;
+//  * C(G') \ C(G) = Lambda_del(G', H): Algorithm 7 over those cliques, whose
+//    stored-set test "c' in C(G')" takes its equivalent form (c' is a clique
+//    of G' that no outside vertex is G'-adjacent to all of), since C(G') is
+//    what is being computed.
+// Canonicalisation as for additions, except that pairs not in G (instead of
+// pairs already in G) are skipped.  Returns -1 for a self-loop or id >= n
+// (state untouched) and -2 if a removed clique is missing from the stored set
+// or an added one is already in it.  In `res`, n_new / hash_new describe the
+// cliques that become maximal (added) and n_del / hash_del those that stop
+// being maximal (removed).
+int orc_imce_remove(void* h, const uint32_t* src, const uint32_t* dst, uint64_t rho, orc_imce_result* res,
+                    CliqueOut* added_out, CliqueOut* removed_out) {
+  ImceState* st = (ImceState*)h;
+  const uint64_t n = st->n;
+  for (uint64_t i = 0; i < rho; ++i)
+    if (src[i] >= n || dst[i] >= n || src[i] == dst[i]) return -1;
+  std::map<std::pair<uint32_t, uint32_t>, uint64_t> index;
+  std::vector<std::pair<uint32_t, uint32_t>> H;
+  uint64_t skipped = 0;
+  for (uint64_t i = 0; i < rho; ++i) {
+    uint32_t a = std::min(src[i], dst[i]), b = std::max(src[i], dst[i]);
+    if (!st->A.has(a, b) || index.count({a, b})) { ++skipped; continue; }
+    index[{a, b}] = H.size();
+    H.push_back({a, b});
+  }
+  // Lambda_new(G', H) on G = G' + H: the cliques that stop being maximal
+  Sink gone;
+  gone.keep = true;
+  for (uint64_t i = 0; i < H.size(); ++i) {
+    uint32_t u = H[i].first, v = H[i].second;
+    VSet common = intersect(st->A.rows[u], st->A.nb(v), st->A.deg(v));
+    std::vector<uint32_t> K{u, v};
+    Exclusion ex;
+    ex.index = &index;
+    ex.before = i;
+    ttt(st->A, K, common, VSet(), gone, ex);
+  }
+  for (const VSet& c : gone.cliques)
+    if (!st->C.count(c)) return -2;
+  // G' = G - H
+  for (auto& e : H) {
+    erase_sorted(st->A.rows[e.first], e.second);
+    erase_sorted(st->A.rows[e.second], e.first);
+  }
+  // Lambda_del(G', H): edge-free subsets of the removed cliques, maximal in G'
+  std::set<VSet> added;
+  for (const VSet& c : gone.cliques)
+    for (const VSet& cp : edge_free_subsets(c, index))
+      if (maximal_in(st->A, cp)) added.insert(cp);
+  for (const VSet& c : added)
+    if (st->C.count(c)) return -2;
+  orc_imce_result r{};
+  r.n_applied = H.size();
+  r.n_skipped = skipped;
+  r.n_del = gone.count;
+  r.hash_del = gone.hash;
+  r.n_new = added.size();
+  for (const VSet& c : added) r.hash_new += clique_hash(c.data(), c.size());
+  for (const VSet& c : gone.cliques) st->C.erase(c);
+  for (const VSet& c : added) st->C.insert(c);
+  st->count = st->count + r.n_new - r.n_del;
+  st->hash = st->hash + r.hash_new - r.hash_del;
+  r.count = st->count;
+  r.set_hash = st->hash;
+  *res = r;
+  if (added_out) {
+    std::vector<VSet> v(added.begin(), added.end());
+    write_cliques(v, added_out);
+  }
+  if (removed_out) {
+    std::vector<VSet> v = gone.cliques;
+    std::sort(v.begin(), v.end());
+    write_cliques(v, removed_out);
   }
   return 0;
 }

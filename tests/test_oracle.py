@@ -425,6 +425,94 @@ def test_imce_batch_canonicalisation():
     assert (r["n_applied"], r["n_new"], r["n_del"]) == (0, 0, 0)
 
 
+# --------------------------------------------------------------------------
+# decremental step (Section 5.3): deletions by reduction to additions
+
+@pytest.mark.parametrize("name", ["fig3_imce.json", "cut_figure_imce.json"])
+def test_deletion_undoes_the_worked_examples(name):
+    # replay the example forwards, then delete its batches in reverse order:
+    # each deletion removes exactly the batch's new cliques and restores
+    # exactly the cliques it had subsumed, back to the initial clique set
+    fx = _load(name)
+    g = gg.from_edge_list(fx["n"], _as_ids(fx, fx["edges"]))
+    st = O.Imce(g)
+    start = st.snapshot(cliques=True)
+    for b in fx["batches"]:
+        add = _as_ids(fx, b["add"])
+        st.add([a for a, _ in add], [x for _, x in add])
+    for b in reversed(fx["batches"]):
+        rem = _as_ids(fx, b["add"])
+        r = st.remove([x for _, x in rem], [a for a, _ in rem], cliques=True)
+        assert r["del"] == sorted(_as_ids(fx, b["new"]))
+        assert r["new"] == sorted(_as_ids(fx, b["subsumed"]))
+    assert st.snapshot(cliques=True) == start
+
+
+@pytest.mark.parametrize("n", [3, 5, 12, 30])
+def test_deletion_from_a_complete_graph(n):
+    # K_n minus one edge: the one clique goes, the two cliques missing one end come
+    st = O.Imce(gg.complete(n))
+    r = st.remove([n - 1], [0], cliques=True)
+    assert r["del"] == [tuple(range(n))]
+    assert r["new"] == sorted([tuple(range(1, n)), tuple(range(n - 1))])
+    assert (r["n_new"], r["n_del"], r["count"]) == (2, 1, 2)
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_deletion_from_moon_moser(k):
+    # K_{3,...,3} minus an edge between two parts: the 3^(k-2) transversals
+    # through both ends go, and nothing new is maximal (each leftover extends
+    # by the removed end's part mates)
+    st = O.Imce(gg.moon_moser(3 * k))
+    r = st.remove([0], [3])  # vertex 0 of part 0, vertex 3 of part 1
+    assert (r["n_del"], r["n_new"]) == (3 ** (k - 2), 0)
+    assert r["count"] == 3 ** k - 3 ** (k - 2)
+
+
+def test_deletion_canonicalisation():
+    g = gg.from_edge_list(6, [(0, 1), (1, 2), (3, 4)])
+    st = O.Imce(g)
+    before = st.snapshot()
+    with pytest.raises(ValueError):
+        st.remove([0], [0])
+    with pytest.raises(ValueError):
+        st.remove([0], [9])
+    assert st.snapshot() == before  # state unchanged by rejected batches
+    r = st.remove([1, 0, 2, 4, 5], [0, 1, 0, 3, 0])  # (1,0) once, repeat, two non-edges, (4,3)
+    assert (r["n_applied"], r["n_skipped"]) == (2, 3)
+    r = st.remove([], [])
+    assert (r["n_applied"], r["n_new"], r["n_del"]) == (0, 0, 0)
+
+
+def test_deletion_streams_equal_recompute_and_diff():
+    for seed in range(10):
+        n = 12 + seed * 2
+        g = gg.er(n, 0.25 + 0.02 * seed, seed=seed)
+        st = O.Imce(g)
+        cur = g
+        for s, d in gg.deletion_stream(g, 4, 1, 8, seed=70 + seed, junk_fraction=0.3):
+            nxt = gg.remove_edges(cur, s, d)
+            want_new, want_del = _recompute_diff(cur, nxt)
+            r = st.remove(s, d, cliques=True)
+            assert r["new"] == want_new and r["del"] == want_del
+            assert (r["count"], r["set_hash"]) == O.mce_root(nxt)[:2]
+            cur = nxt
+
+
+def test_deletion_of_an_added_batch_is_its_inverse():
+    for seed in range(8):
+        g = gg.er(40, 0.12, seed=200 + seed)
+        st = O.Imce(g)
+        for s, d in gg.edge_stream(g, 3, 2, 10, seed=300 + seed):
+            before = st.snapshot()
+            a = st.add(s, d, cliques=True)
+            r = st.remove(d, s, cliques=True)
+            assert r["del"] == a["new"] and r["new"] == a["del"]
+            assert (r["n_applied"], r["hash_new"], r["hash_del"]) == (a["n_applied"], a["hash_del"], a["hash_new"])
+            assert st.snapshot() == before
+            st.add(s, d)
+
+
 def _recompute_diff(g_old, g_new):
     old = set(O.mce_root(g_old, cliques=True)[3])
     new = set(O.mce_root(g_new, cliques=True)[3])
