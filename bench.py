@@ -193,21 +193,10 @@ def ownership_and_imbalance(m, dg, ref, launch, base_rank: str):
         log("ownership %s: rank %.1f ms, build %.1f ms, enum %.1f ms, %d nodes" % (
             rank, r["rank_ms"], r["build_ms"], r["enum_ms"], r["nodes_total"]))
         if per_vertex:
-            def share(x):
-                x = np.sort(x.astype(np.float64))[::-1]
-                tot = x.sum()
-                if tot == 0:
-                    return 0.0
-                k = int(np.searchsorted(np.cumsum(x), 0.9 * tot)) + 1
-                return k / float(x.size)
+            from paper_2001_11433_amd import diagnostics
             nodes = r["nodes_v"].cpu().numpy().view(np.uint64)
             count = r["count_v"].cpu().numpy().view(np.uint64)
-            out["imbalance"] = {
-                "rank": rank, "subproblems": int(nodes.size),
-                "share_of_subproblems_for_90pct_nodes": share(nodes),
-                "share_of_subproblems_for_90pct_cliques": share(count),
-                "largest_subproblem_share_of_nodes": float(nodes.max()) / float(nodes.sum()),
-            }
+            out["imbalance"] = dict(rank=rank, **diagnostics.imbalance(nodes, count))
     return out
 
 

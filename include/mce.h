@@ -163,13 +163,19 @@ typedef struct {
   uint64_t n_cliques, n_verts;
 } mce_clique_buf;
 
-/* Optional per-subproblem outputs, device arrays of n entries each (any may be
- * NULL): search nodes, cliques and H(cliques) of subproblem v.  Node counts
- * are the labels of the learned cost model. */
+/* Optional outputs (any pointer may be NULL).  nodes / count / hash: device
+ * arrays of n entries, the search nodes, cliques and H(cliques) of
+ * subproblem v; node counts are the labels of the learned cost model.
+ * size_hist: device array of hist_len >= 2 entries, overwritten with the
+ * clique-size distribution the paper reports per graph (Section 6.1):
+ * size_hist[k] = number of maximal cliques with k vertices, cliques of
+ * hist_len - 1 or more vertices counted in the last entry. */
 typedef struct {
   uint64_t* nodes;
   uint64_t* count;
   uint64_t* hash;
+  uint64_t* size_hist;
+  uint64_t hist_len;
 } mce_per_vertex;
 
 /* All maximal cliques of `g` (Algorithm 4 over Algorithm 1).
@@ -222,6 +228,18 @@ int imce_create(const mce_csr* g, const mce_opts* opts, imce_state** out, mce_re
  * batch edges inside it. */
 int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
                    imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
+
+/* Deletes the batch H = {(src[i], dst[i])} (Section 5.3: the reduction of a
+ * deletion to the incremental case on G - H, since G = (G - H) + H).  The
+ * cliques of G that hold an edge of H stop being maximal (del_cl, n_del,
+ * hash_del; Algorithms 5 and 8 run on G), and those of their subsets free of
+ * H edges that are maximal in G - H become maximal (new_cl, n_new, hash_new;
+ * Algorithm 7 with its membership test in the form "maximal in G - H").
+ * Canonicalisation as in imce_add_edges except that pairs that are not edges
+ * of G (and repeats) are skipped.  Same errors, envelope and all-or-nothing
+ * commit as imce_add_edges. */
+int imce_remove_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                      imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
 
 /* Current graph: n and the number of stored adjacency entries (2m). */
 int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash);

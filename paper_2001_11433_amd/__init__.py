@@ -59,7 +59,8 @@ class _CliqueBuf(ctypes.Structure):
 
 
 class _PerVertex(ctypes.Structure):
-    _fields_ = [("nodes", ctypes.c_void_p), ("count", ctypes.c_void_p), ("hash", ctypes.c_void_p)]
+    _fields_ = [("nodes", ctypes.c_void_p), ("count", ctypes.c_void_p), ("hash", ctypes.c_void_p),
+                ("size_hist", ctypes.c_void_p), ("hist_len", ctypes.c_uint64)]
 
 
 class _ImceResult(ctypes.Structure):
@@ -69,7 +70,8 @@ class _ImceResult(ctypes.Structure):
                 ("nodes", ctypes.c_uint64), ("handed", ctypes.c_uint64), ("compact_ms", ctypes.c_double)]
 
 
-EXPORTS = ("mce_static", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_info",
+EXPORTS = ("mce_static", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_remove_edges",
+           "imce_info",
            "imce_destroy", "mce_strerror", "mce_last_error", "mce_mlp_param_count", "mce_mlp_forward",
            "mce_mlp_forward_bf16", "mce_mlp_grad", "mce_mlp_adam", "mce_mlp_fit_norm", "mce_mlp_to_bf16",
            "mce_mlp_labels")
@@ -96,6 +98,7 @@ def lib():
         L.imce_add_edges.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                      ctypes.c_int, ctypes.POINTER(_ImceResult), ctypes.POINTER(_CliqueBuf),
                                      ctypes.POINTER(_CliqueBuf)]
+        L.imce_remove_edges.argtypes = L.imce_add_edges.argtypes
         L.imce_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.imce_destroy.argtypes = [ctypes.c_void_p]
@@ -193,13 +196,15 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
                split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False,
-               compact_order: int = 0) -> Dict[str, object]:
+               compact_order: int = 0, size_hist: int = 0) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
     max_cand, rank_ms, build_ms, enum_ms, retries; with cliques=True also
     'cliques' (sorted list of sorted tuples); with per_vertex=True the device
-    tensors 'nodes_v', 'count_v', 'hash_v' (int64 views of uint64)."""
+    tensors 'nodes_v', 'count_v', 'hash_v' (int64 views of uint64); with
+    size_hist=L > 1 also 'size_hist', a numpy uint64 array of L entries (entry
+    k = maximal cliques with k vertices, the last entry L-1 or more)."""
     torch = _torch()
     dg = _as_device_graph(g)
     csr = dg.csr()
@@ -208,10 +213,17 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     res = _Result()
     pv = None
     tensors = {}
+    hist = None
     if per_vertex:
         for k in ("nodes_v", "count_v", "hash_v"):
             tensors[k] = torch.zeros(max(dg.n, 1), dtype=torch.int64, device=dg.row_ptr.device)
-        pv = _PerVertex(tensors["nodes_v"].data_ptr(), tensors["count_v"].data_ptr(), tensors["hash_v"].data_ptr())
+    if size_hist:
+        hist = torch.zeros(int(size_hist), dtype=torch.int64, device=dg.row_ptr.device)
+    if per_vertex or size_hist:
+        pv = _PerVertex(tensors["nodes_v"].data_ptr() if per_vertex else None,
+                        tensors["count_v"].data_ptr() if per_vertex else None,
+                        tensors["hash_v"].data_ptr() if per_vertex else None,
+                        hist.data_ptr() if hist is not None else None, int(size_hist))
     out = {}
     if cliques:
         cc, cv = cap_cliques, cap_verts
@@ -240,6 +252,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     if per_vertex:
         for k, t in tensors.items():
             out[k] = t[:dg.n]
+    if hist is not None:
+        out["size_hist"] = hist.cpu().numpy().view(np.uint64)
     return out
 
 
@@ -308,14 +322,24 @@ class ImceState:
         return {"n": n.value, "nnz": nnz.value, "count": c.value, "set_hash": h.value}
 
     def add(self, src, dst, cliques: bool = False, cap_cliques: int = 1 << 14, cap_verts: int = 1 << 18):
+        """imce_add_edges: 'new' / 'del' are the cliques that become / stop
+        being maximal."""
+        return self._update(lib().imce_add_edges, src, dst, cliques, cap_cliques, cap_verts)
+
+    def remove(self, src, dst, cliques: bool = False, cap_cliques: int = 1 << 14, cap_verts: int = 1 << 18):
+        """imce_remove_edges (deletions by reduction to additions): same result
+        layout as add."""
+        return self._update(lib().imce_remove_edges, src, dst, cliques, cap_cliques, cap_verts)
+
+    def _update(self, fn, src, dst, cliques, cap_cliques, cap_verts):
         torch = self._torch
         s = torch.as_tensor(np.ascontiguousarray(np.asarray(src, dtype=np.uint32)).view(np.int32)).cuda()
         d = torch.as_tensor(np.ascontiguousarray(np.asarray(dst, dtype=np.uint32)).view(np.int32)).cuda()
         rho = int(s.numel())
         res = _ImceResult()
         if not cliques:
-            _check(lib().imce_add_edges(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
-                                        ctypes.byref(res), None, None))
+            _check(fn(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
+                      ctypes.byref(res), None, None))
             out = {k: getattr(res, k) for k, _ in _ImceResult._fields_}
             return out
         cc, cv = cap_cliques, cap_verts
@@ -327,8 +351,8 @@ class ImceState:
                 vert = torch.zeros(max(cv, 1), dtype=torch.int32, device="cuda")
                 bufs.append((off, vert))
                 cbs.append(_CliqueBuf(cc, cv, off.data_ptr(), vert.data_ptr(), 1, 0, 0))
-            rc = lib().imce_add_edges(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
-                                      ctypes.byref(res), ctypes.byref(cbs[0]), ctypes.byref(cbs[1]))
+            rc = fn(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
+                    ctypes.byref(res), ctypes.byref(cbs[0]), ctypes.byref(cbs[1]))
             if rc == MCE_ENOSPC:
                 cc = max(cc, int(cbs[0].n_cliques), int(cbs[1].n_cliques))
                 cv = max(cv, int(cbs[0].n_verts), int(cbs[1].n_verts))

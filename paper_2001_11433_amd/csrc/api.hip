@@ -63,6 +63,12 @@ __global__ void k_iota(uint64_t n, uint32_t* a) {
   if (i < n) a[i] = (uint32_t)i;
 }
 
+// Isolated vertices are the cliques of size 1, found by the subproblem sizing
+// (stats[3]); the search tallies every other size.
+__global__ void k_hist_singletons(uint64_t* hist, uint64_t len, const uint64_t* stats) {
+  hist[len > 1 ? 1 : 0] += stats[3];
+}
+
 // Singletons {v} of isolated vertices, for materialised output.
 __global__ void k_emit_isolated(uint64_t n, const uint64_t* __restrict__ rp, uint64_t* ctl, uint64_t* off,
                                 uint32_t* vert, uint64_t cap_c, uint64_t cap_v) {
@@ -252,6 +258,9 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     a.hash_v = j.hash_v;
     a.cl_off = j.cl_off;
     a.cl_vert = j.cl_vert;
+    a.hist = j.hist;
+    a.hist_len = j.hist_len;
+    a.emit_extra = (j.cl_vert || j.hist) ? 1u : 0u;
     a.cap_cliques = j.cap_cliques;
     a.cap_verts = j.cap_verts;
     if (j.max_p + (j.excl ? 2u : 1u) + 2 > kKLds) {
@@ -368,6 +377,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   uint64_t nnz;
   MCE_TRY(stage_csr(g, ws, s, &rp, &col, &nnz));
   if (n == 0) {
+    if (pv && pv->size_hist && pv->hist_len)
+      MCE_TRY_HIP(hipMemsetAsync(pv->size_hist, 0, pv->hist_len * sizeof(uint64_t), s));
     if (cl) {
       cl->n_cliques = 0;
       cl->n_verts = 0;
@@ -376,8 +387,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
         if (cl->on_device) MCE_TRY_HIP(hipMemcpyAsync(cl->off, &z, sizeof(z), hipMemcpyHostToDevice, s));
         else cl->off[0] = 0;
       }
-      MCE_TRY_HIP(hipStreamSynchronize(s));
     }
+    MCE_TRY_HIP(hipStreamSynchronize(s));
     return MCE_OK;
   }
   if (opts.validate) MCE_TRY(validate_csr(n, rp, col, ws, s));
@@ -424,6 +435,12 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   uint64_t* nodes_v = pv ? pv->nodes : nullptr;
   uint64_t* count_v = pv ? pv->count : nullptr;
   uint64_t* hash_v = pv ? pv->hash : nullptr;
+  uint64_t* hist = pv ? pv->size_hist : nullptr;
+  const uint64_t hist_len = pv ? pv->hist_len : 0;
+  if (hist && hist_len < 2) {
+    set_error("size_hist needs hist_len >= 2");
+    return MCE_EINVAL;
+  }
 
   MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
   MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
@@ -511,6 +528,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   job.nodes_v = nodes_v;
   job.count_v = count_v;
   job.hash_v = hash_v;
+  job.hist = hist;
+  job.hist_len = hist_len;
   job.cl_off = cl_off;
   job.cl_vert = cl_vert;
   job.cap_cliques = cl ? cl->cap_cliques : 0;
@@ -524,6 +543,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) job.hand_initial_units = free_b / 4 / 64;
   }
   job.before_launch = [&](uint32_t attempt, uint64_t* ctl_dev) -> int {
+    if (hist) MCE_TRY_HIP(hipMemsetAsync(hist, 0, hist_len * sizeof(uint64_t), s));
     if (attempt > 0) {
       // results of the aborted run are discarded: reset per-vertex outputs
       MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
@@ -539,6 +559,10 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   uint64_t ctl[CTL_WORDS];
   MCE_TRY(run_enum(job, ws.ew, s, ctl, &out->retries));
   MCE_TRY_HIP(hipEventRecord(tm.e[3], s));
+  if (hist) {
+    hipLaunchKernelGGL(k_hist_singletons, dim3(1), dim3(1), 0, s, hist, hist_len, b.stats);
+    MCE_TRY_HIP(hipGetLastError());
+  }
   MCE_TRY_HIP(hipMemcpyAsync(stats, b.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
   MCE_TRY_HIP(hipStreamSynchronize(s));
   out->count = stats[3] + ctl[CTL_COUNT];

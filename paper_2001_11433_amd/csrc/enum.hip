@@ -50,6 +50,7 @@ struct Lds {
   uint64_t cstk[kCFrames * kCF];
   uint32_t kG[kKLds];  // ids of K, roots first
   uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
+  uint64_t hist[kHistLds];  // clique sizes tallied by this wave (when requested)
 };
 
 // LDS of the compact kernel: frames and a K list long enough for a handed-off
@@ -57,7 +58,32 @@ struct Lds {
 struct LdsC {
   uint64_t cstk[kCFrames * kCF];
   uint32_t kG[kHandK + kCFrames + 2];
+  uint64_t hist[kHistLds];
 };
+
+static_assert(kHistLds == kWave, "one LDS histogram bin per lane");
+
+// One clique of k vertices into the size histogram (lane 0 of the wave).
+__device__ __forceinline__ void hist_add(const EnumArgs& a, uint64_t* lhist, uint32_t k) {
+  if (lane_id() == 0) {
+    if (k < kHistLds)
+      lhist[k] += 1;
+    else
+      atomicAdd((unsigned long long*)&a.hist[k < a.hist_len - 1 ? k : a.hist_len - 1], 1ULL);
+  }
+}
+
+__device__ __forceinline__ void hist_clear(const EnumArgs& a, uint64_t* lhist) {
+  if (a.hist) lhist[lane_id()] = 0;
+}
+
+__device__ __forceinline__ void hist_flush(const EnumArgs& a, const uint64_t* lhist) {
+  if (!a.hist) return;
+  __syncthreads();
+  const uint32_t k = (uint32_t)lane_id();
+  const uint64_t c = lhist[k];
+  if (c) atomicAdd((unsigned long long*)&a.hist[k < a.hist_len - 1 ? k : a.hist_len - 1], (unsigned long long)c);
+}
 
 // Per-task tallies.  The algorithmic op count of a node is
 // 3*s*w + 2*|ext|*w + 2*s with w fixed per subproblem, so the task keeps the
@@ -333,10 +359,13 @@ __device__ uint64_t split_root(const EnumArgs& a, const uint32_t* kG, uint64_t* 
 // K is maximal: count it, hash it, and optionally write it out.
 __device__ void store_clique(const EnumArgs& a, uint32_t k, const uint32_t* kG);
 
-__device__ void emit(const EnumArgs& a, Acc& acc, uint64_t zsum, uint32_t k, const uint32_t* kG) {
+__device__ void emit(const EnumArgs& a, Acc& acc, uint64_t* lhist, uint64_t zsum, uint32_t k, const uint32_t* kG) {
   ++acc.tc;
   acc.th += clique_term(zsum, k);
-  if (a.cl_vert) store_clique(a, k, kG);
+  if (a.emit_extra) {
+    if (a.cl_vert) store_clique(a, k, kG);
+    if (a.hist) hist_add(a, lhist, k);
+  }
 }
 
 __device__ void store_clique(const EnumArgs& a, uint32_t k, const uint32_t* kG) {
@@ -419,7 +448,10 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
       if (P == 0) {
         if ((Xp | Xx) == 0) {
           T.clique(zsum, kl);
-          if (a.cl_vert) store_clique(a, kl, kG);
+          if (a.emit_extra) {
+            if (a.cl_vert) store_clique(a, kl, kG);
+            if (a.hist) hist_add(a, L.hist, kl);
+          }
         }
         ext = 0;  // no children: the node is done
       } else {
@@ -459,10 +491,13 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         T.node();
         if (((Xp & rq) | (Xx & rqx)) == 0) {
           T.clique(zsum + readlane64(c.zP, q), kl + 1);
-          if (a.cl_vert) {
-            if (lane == 0) kG[kl] = readlane32(c.gP, q);
-            __syncthreads();  // the K list is read by every lane
-            store_clique(a, kl + 1, kG);
+          if (a.emit_extra) {
+            if (a.cl_vert) {
+              if (lane == 0) kG[kl] = readlane32(c.gP, q);
+              __syncthreads();  // the K list is read by every lane
+              store_clique(a, kl + 1, kG);
+            }
+            if (a.hist) hist_add(a, L.hist, kl + 1);
           }
         }
         continue;
@@ -485,13 +520,16 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         if (!blocked && !excluded) {
           T.node();
           T.clique(zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2);
-          if (a.cl_vert) {
-            if (lane == 0) {
-              kG[kl] = readlane32(c.gP, q);
-              kG[kl + 1] = readlane32(c.gP, w);
+          if (a.emit_extra) {
+            if (a.cl_vert) {
+              if (lane == 0) {
+                kG[kl] = readlane32(c.gP, q);
+                kG[kl + 1] = readlane32(c.gP, w);
+              }
+              __syncthreads();  // the K list is read by every lane
+              store_clique(a, kl + 2, kG);
             }
-            __syncthreads();  // the K list is read by every lane
-            store_clique(a, kl + 2, kG);
+            if (a.hist) hist_add(a, L.hist, kl + 2);
           }
         }
         continue;
@@ -747,6 +785,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   uint32_t since = 0;
   Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
   const uint64_t t_start = now();
+  hist_clear(a, L.hist);
 
   for (;;) {
     uint64_t ref = 0;
@@ -871,7 +910,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
               for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
               xe = ballot(nz) == 0;
             }
-            if (xe) emit(a, acc, zsum, kroot + d, kG);
+            if (xe) emit(a, acc, L.hist, zsum, kroot + d, kG);
             do_pop = true;
           } else {
             if (lane < (int)wp) L.sP[lane] = rP;
@@ -1116,6 +1155,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     tot_h += acc.th;
     tot_ops += acc.ops(wv);
   }
+  hist_flush(a, L.hist);
   if (lane == 0) {
     if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
     if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
@@ -1147,6 +1187,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
   Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
+  hist_clear(a, L.hist);
   for (;;) {
     uint64_t ref = 0;
     const uint64_t tw = now();
@@ -1189,6 +1230,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     tot_h += acc.th;
     tot_ops += acc.ops(wv);
   }
+  hist_flush(a, L.hist);
   if (lane == 0) {
     if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
     if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);

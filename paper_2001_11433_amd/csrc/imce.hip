@@ -17,6 +17,11 @@
 //      exactly, so each subsumed clique is reported once;
 //   5. commit: G <- G', count += |new| - |del|, hash += H(new) - H(del).
 // Any error before step 5 leaves the state unchanged.
+//
+// Deletions (Section 5.3) reduce to the same steps: G' = G - H is built in
+// step 2, the edge subproblems of step 3 run on G (= G' + H) and give the
+// cliques that stop being maximal, and step 4 tests maximality in G' and gives
+// the cliques that become maximal.
 
 #include <hipcub/hipcub.hpp>
 
@@ -77,16 +82,16 @@ __global__ void k_canon(uint64_t rho, const uint32_t* __restrict__ src, const ui
 }
 
 // After a stable sort by key: the first occurrence of each key survives
-// unless the edge is already in G.
+// unless the edge is already in G (additions) or is not in G (deletions).
 __global__ void k_keep(uint64_t rho, const uint64_t* __restrict__ skeys, const uint32_t* __restrict__ sidx, uint64_t n,
-                       const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col, uint64_t* keep) {
+                       const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col, int remove, uint64_t* keep) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= rho) return;
   const uint64_t key = skeys[i];
   bool first = i == 0 || skeys[i - 1] != key;
   const uint32_t a = (uint32_t)(key / n), b = (uint32_t)(key % n);
   bool exists = bsearch_u32(col + rp[a], rp[a + 1] - rp[a], b) >= 0;
-  keep[sidx[i]] = (first && !exists) ? 1 : 0;
+  keep[sidx[i]] = (first && exists == (remove != 0)) ? 1 : 0;
 }
 
 __global__ void k_scatter(uint64_t rho, const uint64_t* __restrict__ keep, const uint64_t* __restrict__ pos,
@@ -138,6 +143,41 @@ __global__ void k_newdeg(uint64_t n, const uint64_t* __restrict__ rp, const uint
 }
 
 __global__ void k_rp_tail(uint64_t n, uint64_t* rpn, const uint64_t* degw) { rpn[n] = rpn[n - 1] + degw[n - 1]; }
+
+// G - H: degrees after the deletions (every batch pair is an edge of G).
+__global__ void k_deldeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ dkeys, uint64_t nd,
+                         uint64_t* degw) {
+  uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  degw[v] = rp[v + 1] - rp[v] - (hi - lo);
+}
+
+// One wave per vertex: its row without the deleted neighbours, order kept.
+__global__ void __launch_bounds__(256) k_remove_rows(uint64_t n, const uint64_t* __restrict__ rp,
+                                                     const uint32_t* __restrict__ col, const uint64_t* __restrict__ dkeys,
+                                                     uint64_t nd, const uint64_t* __restrict__ rpn, uint32_t* coln) {
+  const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = lane_id();
+  if (v >= n) return;
+  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint32_t* row = col + rp[v];
+  const uint64_t d = rp[v + 1] - rp[v];
+  uint32_t* out = coln + rpn[v];
+  uint64_t kept = 0;
+  for (uint64_t j0 = 0; j0 < d; j0 += kWave) {
+    const uint64_t j = j0 + lane;
+    bool keep = j < d;
+    const uint32_t w = keep ? row[j] : 0;
+    if (keep && hi > lo) {
+      const uint64_t k = lower_bound_u64(dkeys + lo, hi - lo, v * n + w);
+      keep = !(k < hi - lo && dkeys[lo + k] == v * n + w);
+    }
+    const uint64_t bm = ballot(keep);
+    if (keep) out[kept + mask_prefix(bm, lane)] = w;
+    kept += (uint64_t)__popcll(bm);
+  }
+}
 
 // One wave per vertex: merge the old row with the vertex's new neighbours.
 __global__ void __launch_bounds__(256) k_merge_rows(uint64_t n, const uint64_t* __restrict__ rp,
@@ -740,8 +780,18 @@ int copy_cliques_out(mce_clique_buf* out, const uint64_t* off, const uint32_t* v
   return MCE_OK;
 }
 
-int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
-                   imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+// One batch of edge additions (remove = false) or deletions (remove = true).
+// A deletion is the reduction of Section 5.3: with G' = G - H, G = G' + H, so
+// the edge-subproblem search over G finds Lambda_new(G', H) = the cliques that
+// stop being maximal, and the subsumed pass over G' finds Lambda_del(G', H) =
+// the cliques that become maximal.  The same kernels run with the roles of
+// the two CSR buffers swapped: the search always runs on the graph that holds
+// H, the maximality test on the graph without it.
+int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl, bool remove) {
+  // the search's cliques and the subsumed pass's cliques, as the caller names them
+  mce_clique_buf* search_cl = remove ? del_cl : new_cl;
+  mce_clique_buf* sub_cl = remove ? new_cl : del_cl;
   hipStream_t s = (hipStream_t)st->opts.hip_stream;
   std::memset(res, 0, sizeof(*res));
   const uint64_t n = st->n;
@@ -801,7 +851,7 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   MCE_TRY(sort_pairs_u64_u32(st, st->keys.as<uint64_t>(), st->idx.as<uint32_t>(), st->keys2.as<uint64_t>(),
                              st->idx2.as<uint32_t>(), rho, s, &skeys, &sidx));
   hipLaunchKernelGGL(k_keep, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, skeys, sidx, n, rp, col,
-                     st->keep.as<uint64_t>());
+                     remove ? 1 : 0, st->keep.as<uint64_t>());
   MCE_TRY_HIP(hipGetLastError());
   MCE_TRY(device_exclusive_scan(st->keep.as<uint64_t>(), st->pos.as<uint64_t>(), rho, st->scan_tmp, st->scan_bytes, s));
   uint64_t lastpos = 0, lastkeep = 0;
@@ -845,18 +895,29 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
 
   // 2. G' = G + H
   const int nxt = st->cur ^ 1;
-  const uint64_t nnz2 = st->nnz + nd;
+  const uint64_t nnz2 = remove ? st->nnz - nd : st->nnz + nd;
   MCE_TRY(st->degw.ensure(n * 8));
   MCE_TRY(st->rp[nxt].ensure((n + 1) * 8));
   MCE_TRY(st->col[nxt].ensure(std::max<uint64_t>(nnz2, 1) * 4));
   uint64_t* rpn = st->rp[nxt].as<uint64_t>();
   uint32_t* coln = st->col[nxt].as<uint32_t>();
-  hipLaunchKernelGGL(k_newdeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
+  if (remove)
+    hipLaunchKernelGGL(k_deldeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
+  else
+    hipLaunchKernelGGL(k_newdeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
   MCE_TRY_HIP(hipGetLastError());
   MCE_TRY(device_exclusive_scan(st->degw.as<uint64_t>(), rpn, n, st->scan_tmp, st->scan_bytes, s));
   hipLaunchKernelGGL(k_rp_tail, dim3(1), dim3(1), 0, s, n, rpn, st->degw.as<uint64_t>());
-  hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
+  if (remove)
+    hipLaunchKernelGGL(k_remove_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
+  else
+    hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
   MCE_TRY_HIP(hipGetLastError());
+  // the graph that holds H (searched) and the one without it (maximality test)
+  const uint64_t* srp = remove ? rp : rpn;
+  const uint32_t* scol = remove ? col : coln;
+  const uint64_t* mrp = remove ? rpn : rp;
+  const uint32_t* mcol = remove ? coln : col;
 
   // 3. new cliques: one edge subproblem per applied edge
   MCE_TRY(st->p.ensure(m * 4));
@@ -869,7 +930,7 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   MCE_TRY(st->stats.ensure(8 * 8));
   MCE_TRY_HIP(hipMemsetAsync(st->stats.p, 0, 64, s));
   hipLaunchKernelGGL(k_edge_sizes, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
-                     st->ev.as<uint32_t>(), rpn, coln, st->p.as<uint32_t>(), st->x.as<uint32_t>(),
+                     st->ev.as<uint32_t>(), srp, scol, st->p.as<uint32_t>(), st->x.as<uint32_t>(),
                      st->words.as<uint64_t>(), st->gwords.as<uint64_t>(), st->stats.as<uint64_t>());
   MCE_TRY_HIP(hipGetLastError());
   MCE_TRY(device_exclusive_scan(st->words.as<uint64_t>(), st->off.as<uint64_t>(), m, st->scan_tmp, st->scan_bytes, s));
@@ -891,10 +952,10 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   MCE_TRY(st->gids.ensure(gw * 4));
   MCE_TRY_HIP(hipMemsetAsync(st->arena.p, 0, aw * 8, s));
   hipLaunchKernelGGL(k_edge_gids, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
-                     st->ev.as<uint32_t>(), rpn, coln, st->goff.as<uint64_t>(), st->gids.as<uint32_t>());
+                     st->ev.as<uint32_t>(), srp, scol, st->goff.as<uint64_t>(), st->gids.as<uint32_t>());
   const uint32_t row_chunks = (uint32_t)std::max<uint64_t>((stats[0] + kEdgeRowsPerWave - 1) / kEdgeRowsPerWave, 1);
   hipLaunchKernelGGL(k_edge_rows, dim3(blocks_for(m * 64, 256), row_chunks), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
-                     st->ev.as<uint32_t>(), rpn, coln, st->p.as<uint32_t>(), st->off.as<uint64_t>(),
+                     st->ev.as<uint32_t>(), srp, scol, st->p.as<uint32_t>(), st->off.as<uint64_t>(),
                      st->goff.as<uint64_t>(), st->gids.as<uint32_t>(), dk, di, nd, n, st->arena.as<uint64_t>());
   hipLaunchKernelGGL(k_iota32, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, st->order.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
@@ -945,7 +1006,7 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
     st->cap_nc = std::max(st->cap_nc, nc);
     st->cap_nv = std::max(st->cap_nv, nv);
   }
-  const uint64_t n_new = ctl[CTL_COUNT], h_new = ctl[CTL_HASH];
+  const uint64_t n_srch = ctl[CTL_COUNT], h_srch = ctl[CTL_HASH];
   const uint64_t nc_new = ctl[CTL_CLQ] >> 32, nv_new = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
   MCE_TRY_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, st->new_off.as<uint64_t>() + nc_new, nv_new);
@@ -972,18 +1033,18 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
       uint32_t* defer = st->sdefer.as<uint32_t>();
       uint32_t* big = st->sbig.as<uint32_t>();
       hipLaunchKernelGGL((k_subsumed<kSubFastS, kSubFastPairs>), dim3(grid), dim3(64), 0, s, nc_new, nullptr, nullptr,
-                         defer, big, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m, dk,
+                         defer, big, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, mrp, mcol, hk, m, dk,
                          nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       hipLaunchKernelGGL((k_subsumed<kSubMaxS, kSubMaxPairs>), dim3(1024), dim3(64), 0, s, nc_new, defer, sc + 2,
-                         nullptr, nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, rp, col, hk, m,
+                         nullptr, nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, mrp, mcol, hk, m,
                          dk, nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       // new cliques above kSubMaxK vertices (rare: a batch edge inside a very large clique)
       hipLaunchKernelGGL(k_subsumed_big, dim3(256), dim3(64), 0, s, big, sc + 3, st->new_off.as<uint64_t>(),
-                         st->new_vert.as<uint32_t>(), n, rp, col, dk, nd, sc, st->cand_off.as<uint64_t>(),
+                         st->new_vert.as<uint32_t>(), n, mrp, mcol, dk, nd, sc, st->cand_off.as<uint64_t>(),
                          st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
     }
@@ -1008,7 +1069,7 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   MCE_TRY(st->uniq.ensure(4 * 8));
   MCE_TRY_HIP(hipMemsetAsync(st->uniq.p, 0, 32, s));
   uint64_t del_cap_c = 0, del_cap_v = 0;
-  if (del_cl) {
+  if (sub_cl) {
     del_cap_c = nvcand ? ncand : 0;
     del_cap_v = nvcand;
     MCE_TRY(st->del_off.ensure((ncand + 1) * 8));
@@ -1028,25 +1089,25 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
                                st->cid2.as<uint32_t>(), ncand, s, &sh, &sid));
     hipLaunchKernelGGL(k_dedup, dim3(blocks_for(ncand, 256)), dim3(256), 0, s, ncand, sh, sid,
                        st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), nvcand,
-                       st->uniq.as<uint64_t>(), del_cl ? st->del_off.as<uint64_t>() : nullptr,
-                       del_cl ? st->del_vert.as<uint32_t>() : nullptr, del_cap_c, del_cap_v);
+                       st->uniq.as<uint64_t>(), sub_cl ? st->del_off.as<uint64_t>() : nullptr,
+                       sub_cl ? st->del_vert.as<uint32_t>() : nullptr, del_cap_c, del_cap_v);
     MCE_TRY_HIP(hipGetLastError());
     MCE_TRY_HIP(hipMemcpyAsync(uctl, st->uniq.p, 24, hipMemcpyDeviceToHost, s));
   }
   MCE_TRY_HIP(hipEventRecord(ev[2], s));
   MCE_TRY_HIP(hipStreamSynchronize(s));
-  const uint64_t n_del = uctl[0], h_del = uctl[1];
+  const uint64_t n_sub = uctl[0], h_sub = uctl[1];
 
   // caller buffers: report sizes; too small -> no commit
   int rc = MCE_OK;
-  if (new_cl) {
-    int r = copy_cliques_out(new_cl, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), nc_new, nv_new, s);
+  if (search_cl) {
+    int r = copy_cliques_out(search_cl, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), nc_new, nv_new, s);
     if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
     else if (r != MCE_OK) return r;
   }
-  if (del_cl) {
+  if (sub_cl) {
     const uint64_t dnc = uctl[2] >> 32, dnv = uctl[2] & 0xFFFFFFFFULL;
-    int r = copy_cliques_out(del_cl, st->del_off.as<uint64_t>(), st->del_vert.as<uint32_t>(), dnc, dnv, s);
+    int r = copy_cliques_out(sub_cl, st->del_off.as<uint64_t>(), st->del_vert.as<uint32_t>(), dnc, dnv, s);
     if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
     else if (r != MCE_OK) return r;
   }
@@ -1059,12 +1120,12 @@ int add_edges_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
   // 5. commit
   st->cur = nxt;
   st->nnz = nnz2;
-  st->count = st->count + n_new - n_del;
-  st->hash = st->hash + h_new - h_del;
-  res->n_new = n_new;
-  res->n_del = n_del;
-  res->hash_new = h_new;
-  res->hash_del = h_del;
+  res->n_new = remove ? n_sub : n_srch;
+  res->n_del = remove ? n_srch : n_sub;
+  res->hash_new = remove ? h_sub : h_srch;
+  res->hash_del = remove ? h_srch : h_sub;
+  st->count = st->count + res->n_new - res->n_del;
+  st->hash = st->hash + res->hash_new - res->hash_del;
   res->count = st->count;
   res->set_hash = st->hash;
   MCE_TRY_HIP(hipEventRecord(ev[3], s));
@@ -1167,7 +1228,16 @@ int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
     set_error("NULL state or result");
     return MCE_EINVAL;
   }
-  return add_edges_impl(st, src, dst, rho, on_device, out, new_cl, del_cl);
+  return update_impl(st, src, dst, rho, on_device, out, new_cl, del_cl, false);
+}
+
+int imce_remove_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                      imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+  if (!st || !out) {
+    set_error("NULL state or result");
+    return MCE_EINVAL;
+  }
+  return update_impl(st, src, dst, rho, on_device, out, new_cl, del_cl, true);
 }
 
 int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash) {

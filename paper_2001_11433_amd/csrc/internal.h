@@ -102,7 +102,14 @@ struct EnumArgs {
                          // a record that passes both checks)
   uint32_t* kbig;        // per-wave K lists of kKBig entries (gridDim.x of them), for subproblems with
                          // |cand| + |K at the root| + 2 > 512; null when no subproblem needs them
+  uint64_t* hist;        // clique-size histogram (nullable), hist_len entries, last = hist_len - 1 or more
+  uint64_t hist_len;
+  uint32_t emit_extra;   // nonzero when cliques are written out or tallied by size (cl_vert or hist)
 };
+
+// Sizes below this are tallied per wave in LDS and flushed at exit; larger
+// ones go to the histogram with device atomics.
+constexpr uint32_t kHistLds = 64;
 
 // A node is handed off only when its K list has at most kHandK vertices.
 constexpr uint32_t kHandK = 64;
@@ -171,6 +178,8 @@ struct EnumJob {
   uint64_t max_p, max_frame;
   bool excl;               // edge subproblems with excluded edges
   uint64_t *nodes_v, *count_v, *hash_v;
+  uint64_t* hist = nullptr;  // clique-size histogram (nullable), zeroed by the caller
+  uint64_t hist_len = 0;
   uint64_t* cl_off;
   uint32_t* cl_vert;
   uint64_t cap_cliques, cap_verts;

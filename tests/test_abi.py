@@ -86,3 +86,32 @@ def test_header_compiles_as_c99(tmp_path):
     inc = os.path.join(ROOT, "include")
     subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I", inc, str(src)],
                    check=True)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # sizes and field offsets of the public structs as a C compiler lays them
+    # out, against the ctypes mirrors the binding passes through the ABI
+    import shutil
+    import subprocess
+    import paper_2001_11433_amd as m
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mce_opts": m._Opts, "mce_result": m._Result, "mce_clique_buf": m._CliqueBuf,
+               "mce_per_vertex": m._PerVertex, "imce_result": m._ImceResult, "mce_csr": m._Csr}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mce.h"', "int main(void) {"]
+    for cname, cty in structs.items():
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cty._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    for cname, cty in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cty), cname
+        for fname, _ in cty._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(cty, fname).offset, (cname, fname)

@@ -1,5 +1,7 @@
 """Host-side logic that needs no GPU: latency percentiles, tuner keys."""
 
+import numpy as np
+
 import graphgen as gg
 
 
@@ -69,3 +71,34 @@ def test_bench_issue_fractions_are_tied_to_the_kernel_sources(monkeypatch):
         assert 0 < got["salu_frac"] < 1.05 and 0 < got["valu_frac"] < 1.05
     monkeypatch.setattr(bench, "kernel_sources_digest", lambda: "0" * 16)
     assert bench.measured_issue() is None
+
+
+def test_imbalance_shares_closed_forms():
+    from paper_2001_11433_amd import diagnostics as D
+    # equal work: 90 % of it needs 90 % of the subproblems
+    assert D.smallest_share_holding(np.ones(10)) == 0.9
+    # one subproblem holds everything
+    x = np.zeros(1000)
+    x[17] = 5.0
+    assert D.smallest_share_holding(x) == 1 / 1000
+    # 91 % in one, the rest spread: one subproblem suffices; at 95 % more are needed
+    y = np.full(101, 0.09)
+    y[0] = 91.0
+    assert D.smallest_share_holding(y) == 1 / 101
+    assert D.smallest_share_holding(y, 0.95) == (1 + 45) / 101
+    # order of the input does not matter; empty and all-zero inputs give 0
+    rng = np.random.default_rng(0)
+    z = rng.pareto(1.5, 5000)
+    assert D.smallest_share_holding(z) == D.smallest_share_holding(rng.permutation(z))
+    assert D.smallest_share_holding([]) == 0.0 and D.smallest_share_holding(np.zeros(4)) == 0.0
+    r = D.imbalance(x, x)
+    assert r["share_of_subproblems_for_90pct_nodes"] == 1 / 1000 and r["largest_subproblem_share_of_nodes"] == 1.0
+
+
+def test_size_distribution_summary():
+    from paper_2001_11433_amd import diagnostics as D
+    h = np.zeros(10, np.uint64)
+    h[2], h[3], h[7] = 6, 3, 1
+    s = D.size_distribution(h)
+    assert s["bins"] == {2: 6, 3: 3, 7: 1} and s["cliques"] == 10 and s["largest"] == 7
+    assert abs(s["mean"] - (12 + 9 + 7) / 10) < 1e-12

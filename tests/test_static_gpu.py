@@ -268,3 +268,46 @@ def test_feature_kernel(m):
     walks = np.bincount(src, weights=deg[g.col] - 1, minlength=g.n)
     want = np.log1p(np.stack([deg, core, tri, walks], 1))
     assert np.allclose(f, want, rtol=1e-6, atol=1e-6)
+
+
+HIST_GRAPHS = [
+    ("er2000", lambda: gg.er(2000, 0.01, seed=0)),
+    ("rmat11", lambda: gg.rmat(11, 16, 0.57, 0.19, 0.19, seed=3)),
+    ("communities", lambda: gg.plant_communities(gg.chung_lu(3000, 2.1, 8, seed=5), count=6, smin=30, smax=60,
+                                                 p=0.9, seed=6)),
+    ("moon_moser24", lambda: gg.moon_moser(24)),
+    ("K600+isolated", lambda: gg.disjoint_union(gg.complete(600), gg.edgeless(5))),
+]
+
+
+@pytest.mark.parametrize("name,make", HIST_GRAPHS, ids=[h[0] for h in HIST_GRAPHS])
+@pytest.mark.parametrize("rank", ["degree", "degeneracy"])
+def test_clique_size_histogram(m, name, make, rank):
+    # the distribution of maximal-clique sizes (Section 6.1) against the
+    # oracle's, bin by bin; its sum is the clique count
+    g = make()
+    got = m.mce_static(g, rank=rank, size_hist=O.HIST_LEN)
+    want = O.mce_parmce(g, rank, threads=8)
+    assert np.array_equal(got["size_hist"], want.sizes)
+    assert int(got["size_hist"].sum()) == got["count"] == want.count
+    # a short histogram folds every larger size into its last bin
+    short = m.mce_static(g, rank=rank, size_hist=4)["size_hist"]
+    assert list(short[:3]) == list(want.sizes[:3]) and short[3] == want.sizes[3:].sum()
+
+
+def test_clique_size_histogram_with_in_place_compact_search(m):
+    g = HIST_GRAPHS[2][1]()
+    want = O.mce_parmce(g, "degree", threads=8)
+    for kw in ({"inline_compact": True}, {"waves_per_cu": 1, "donate_interval": 16}):
+        got = m.mce_static(g, rank="degree", size_hist=O.HIST_LEN, cliques=True, **kw)
+        assert np.array_equal(got["size_hist"], want.sizes), kw
+
+
+def test_imbalance_shares_from_gpu_outputs(m):
+    # the Figure 2 analog computed from the library's per-subproblem outputs
+    # equals the one computed from the oracle's
+    from paper_2001_11433_amd import diagnostics as D
+    g = gg.rmat(11, 16, 0.57, 0.19, 0.19, seed=3)
+    got = m.mce_static(g, rank="degeneracy", per_vertex=True)
+    want = O.mce_parmce(g, "degeneracy", threads=8)
+    assert D.imbalance(_u64(got["nodes_v"]), _u64(got["count_v"])) == D.imbalance(want.nodes_v, want.count_v)
