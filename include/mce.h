@@ -186,6 +186,26 @@ typedef struct {
 int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
                mce_clique_buf* cliques, const mce_per_vertex* per_vertex);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mce_static
+ * with the same arguments, results and errors, except that
+ *   - every work buffer is carved from one fixed scratch array of
+ *     MCE_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its
+ *     first use on that GPU until the process ends; a call whose buffers do
+ *     not fit returns MCE_ENOTSUP and mce_last_error() says how much it asked
+ *     (host-resident inputs and outputs are staged through the scratch too);
+ *   - no device memory is allocated or freed and no HIP events are created:
+ *     rank_ms, build_ms, enum_ms and compact_ms are 0;
+ *   - the tables for handing subtrees between waves are smaller (the results
+ *     are the same).
+ * All calls on one GPU share its scratch, which keeps the last call's
+ * contents; the library runs them one at a time per GPU (together with
+ * mce_static) and clears what each call needs, so calls from several threads
+ * are serialised rather than racing. */
+#define MCE_NOALLOC_SCRATCH_BYTES (256ULL << 20)
+int mce_static_noalloc(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
+                       mce_clique_buf* cliques, const mce_per_vertex* per_vertex);
+
 /* Per-vertex rank metric (Section 4.2) into the device array metric[n]. */
 int mce_rank_metric(const mce_csr* g, mce_rank rank, uint64_t* metric, void* hip_stream);
 

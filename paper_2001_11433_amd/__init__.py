@@ -70,7 +70,7 @@ class _ImceResult(ctypes.Structure):
                 ("nodes", ctypes.c_uint64), ("handed", ctypes.c_uint64), ("compact_ms", ctypes.c_double)]
 
 
-EXPORTS = ("mce_static", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_remove_edges",
+EXPORTS = ("mce_static", "mce_static_noalloc", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_remove_edges",
            "imce_info",
            "imce_destroy", "mce_strerror", "mce_last_error", "mce_mlp_param_count", "mce_mlp_forward",
            "mce_mlp_forward_bf16", "mce_mlp_grad", "mce_mlp_adam", "mce_mlp_fit_norm", "mce_mlp_to_bf16",
@@ -91,6 +91,7 @@ def lib():
         L.mce_last_error.restype = ctypes.c_char_p
         L.mce_static.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.POINTER(_Opts), ctypes.POINTER(_Result),
                                  ctypes.POINTER(_CliqueBuf), ctypes.POINTER(_PerVertex)]
+        L.mce_static_noalloc.argtypes = L.mce_static.argtypes
         L.mce_rank_metric.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.mce_features.argtypes = [ctypes.POINTER(_Csr), ctypes.c_void_p, ctypes.c_void_p]
         L.imce_create.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_void_p),
@@ -196,13 +197,15 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
                split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False,
-               compact_order: int = 0, size_hist: int = 0) -> Dict[str, object]:
+               compact_order: int = 0, size_hist: int = 0, noalloc: bool = False) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
     max_cand, rank_ms, build_ms, enum_ms, retries; with cliques=True also
     'cliques' (sorted list of sorted tuples); with per_vertex=True the device
     tensors 'nodes_v', 'count_v', 'hash_v' (int64 views of uint64); with
+    noalloc=True the call goes to mce_static_noalloc (no device allocation
+    inside the library; the outputs are allocated here, by torch); with
     size_hist=L > 1 also 'size_hist', a numpy uint64 array of L entries (entry
     k = maximal cliques with k vertices, the last entry L-1 or more)."""
     torch = _torch()
@@ -210,6 +213,7 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     csr = dg.csr()
     o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split, compact_waves_per_cu,
               inline_compact, compact_order)
+    entry = lib().mce_static_noalloc if noalloc else lib().mce_static
     res = _Result()
     pv = None
     tensors = {}
@@ -231,8 +235,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
             off = torch.zeros(cc + 1, dtype=torch.int64, device=dg.row_ptr.device)
             vert = torch.zeros(max(cv, 1), dtype=torch.int32, device=dg.row_ptr.device)
             buf = _CliqueBuf(cc, cv, off.data_ptr(), vert.data_ptr(), 1, 0, 0)
-            rc = lib().mce_static(ctypes.byref(csr), RANKS[rank], ctypes.byref(o), ctypes.byref(res),
-                                  ctypes.byref(buf), ctypes.byref(pv) if pv else None)
+            rc = entry(ctypes.byref(csr), RANKS[rank], ctypes.byref(o), ctypes.byref(res),
+                       ctypes.byref(buf), ctypes.byref(pv) if pv else None)
             if rc == MCE_ENOSPC:
                 cc, cv = int(buf.n_cliques), int(buf.n_verts)
                 continue
@@ -245,8 +249,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
         else:
             raise MceError(MCE_ENOSPC, "clique buffer sizing did not converge")
     else:
-        _check(lib().mce_static(ctypes.byref(csr), RANKS[rank], ctypes.byref(o), ctypes.byref(res), None,
-                                ctypes.byref(pv) if pv else None))
+        _check(entry(ctypes.byref(csr), RANKS[rank], ctypes.byref(o), ctypes.byref(res), None,
+                     ctypes.byref(pv) if pv else None))
     out.update({k: getattr(res, k) for k, _ in _Result._fields_ if k not in ("pad", "diag")})
     out["diag"] = list(res.diag)
     if per_vertex:

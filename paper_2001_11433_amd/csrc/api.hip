@@ -25,6 +25,53 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+Carver*& active_carver() {
+  static thread_local Carver* c = nullptr;
+  return c;
+}
+
+int carve(void** p, uint64_t b) {
+  Carver* c = active_carver();
+  *p = c ? c->take(b) : nullptr;
+  if (!*p) {
+    set_error("the call needs more than the %llu bytes of scratch of the allocation-free entry point "
+              "(%llu in use, %llu more asked)", (unsigned long long)(c ? c->cap : 0),
+              (unsigned long long)(c ? c->used : 0), (unsigned long long)b);
+    return MCE_ENOTSUP;
+  }
+  return MCE_OK;
+}
+
+int ensure_temp(void*& tmp, size_t& tmp_bytes, size_t need) {
+  if (need <= tmp_bytes && tmp) return MCE_OK;
+  if (active_carver()) {
+    MCE_TRY(carve(&tmp, std::max<size_t>(need, 256)));
+    tmp_bytes = std::max<size_t>(need, 256);
+    return MCE_OK;
+  }
+  if (tmp) MCE_TRY_HIP(hipFree(tmp));
+  tmp = nullptr;
+  tmp_bytes = 0;
+  MCE_TRY_HIP(hipMalloc(&tmp, need));
+  tmp_bytes = need;
+  return MCE_OK;
+}
+
+namespace {
+__global__ void k_zero32(uint32_t* p, uint64_t words) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+}  // namespace
+
+hipError_t dev_zero(void* p, uint64_t bytes, hipStream_t s) {
+  const uint64_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((words + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero32, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
 namespace {
 
 // Device workspace of the static pipeline; grown on demand, reused across
@@ -84,19 +131,25 @@ __global__ void k_emit_isolated(uint64_t n, const uint64_t* __restrict__ rp, uin
 
 inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
 
+// Device-time events; `on` = false (the allocation-free entry point) creates
+// none and reports 0 ms.
 struct Timer {
   hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
   ~Timer() {
     for (auto& x : e)
       if (x) (void)hipEventDestroy(x);
   }
-  int init() {
-    for (auto& x : e) MCE_TRY_HIP(hipEventCreate(&x));
+  int init(bool enable = true) {
+    on = enable;
+    if (on)
+      for (auto& x : e) MCE_TRY_HIP(hipEventCreate(&x));
     return MCE_OK;
   }
+  hipError_t record(int i, hipStream_t s) { return on ? hipEventRecord(e[i], s) : hipSuccess; }
   double ms(int a, int b) {
     float t = 0;
-    if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0;
+    if (!on || hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0;
     return t;
   }
 };
@@ -147,7 +200,7 @@ int stage_csr(const mce_csr* g, Workspace& ws, hipStream_t s, const uint64_t** r
 
 int validate_csr(uint64_t n, const uint64_t* rp, const uint32_t* col, Workspace& ws, hipStream_t s) {
   MCE_TRY(ws.bad.ensure(sizeof(uint32_t)));
-  MCE_TRY_HIP(hipMemsetAsync(ws.bad.p, 0, sizeof(uint32_t), s));
+  MCE_TRY_HIP(dev_zero(ws.bad.p, sizeof(uint32_t), s));
   uint64_t first = 1;
   if (n) {
     MCE_TRY_HIP(hipMemcpyAsync(&first, rp, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -216,9 +269,9 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
   uint32_t frame_cap = opts.frame_cap ? opts.frame_cap : 128;
   frame_cap = std::min<uint32_t>(frame_cap, (uint32_t)j.max_p + 2);
   frame_cap = std::max<uint32_t>(frame_cap, 2);
-  const uint64_t max_tickets = std::max<uint64_t>(1u << 24, 4 * j.nq);
+  const uint64_t max_tickets = j.max_tickets ? j.max_tickets : std::max<uint64_t>(1u << 24, 4 * j.nq);
   const uint64_t qcap = j.nq + max_tickets;
-  const uint64_t pool_blocks = 1ULL << 16;  // 64 Ki records of 8 KiB, recycled
+  const uint64_t pool_blocks = j.pool_blocks ? j.pool_blocks : 1ULL << 16;  // records of 8 KiB, recycled
   MCE_TRY(w.queue.ensure(qcap * sizeof(uint64_t)));
   MCE_TRY(w.pool.ensure(pool_blocks * kBlockWords * sizeof(uint64_t)));
   MCE_TRY(w.pool_next.ensure(pool_blocks * sizeof(uint32_t)));
@@ -227,7 +280,7 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
   for (uint32_t attempt = 0;; ++attempt) {
     const uint64_t stack_words = (uint64_t)frame_cap * std::max<uint64_t>(j.max_frame + 1, 8);
     MCE_TRY(w.stacks.ensure((uint64_t)grid * stack_words * sizeof(uint64_t)));
-    MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap * sizeof(uint64_t), s));
+    MCE_TRY_HIP(dev_zero(w.queue.p, qcap * sizeof(uint64_t), s));
     MCE_TRY_HIP(launch_queue_fill(j.nq, j.order, j.split, w.queue.as<uint64_t>(), s));
     std::memset(ctl, 0, CTL_WORDS * sizeof(uint64_t));
     ctl[CTL_TAIL] = j.nq;
@@ -300,7 +353,7 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
       if (qcap2 > qcap) MCE_TRY(w.queue.ensure(qcap2 * sizeof(uint64_t)));
       a.queue = w.queue.as<uint64_t>();
       a.qcap = qcap2;
-      MCE_TRY_HIP(hipMemsetAsync(w.queue.p, 0, qcap2 * sizeof(uint64_t), s));
+      MCE_TRY_HIP(dev_zero(w.queue.p, qcap2 * sizeof(uint64_t), s));
       const uint32_t* order = nullptr;
       if (opts.compact_order == 1) {
         // largest candidate set first (then largest fini)
@@ -325,10 +378,10 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
       MCE_TRY_HIP(hipMemcpyAsync(w.ctl.p, ctl, CTL_WORDS * sizeof(uint64_t), hipMemcpyHostToDevice, s));
       const uint32_t cwpc = opts.compact_waves_per_cu ? opts.compact_waves_per_cu : kCompactWavesPerCu;
       Timer tm;
-      MCE_TRY(tm.init());
-      MCE_TRY_HIP(hipEventRecord(tm.e[0], s));
+      MCE_TRY(tm.init(j.timing));
+      MCE_TRY_HIP(tm.record(0, s));
       MCE_TRY_HIP(launch_compact(a, (uint32_t)cu_count() * cwpc, j.excl, s));
-      MCE_TRY_HIP(hipEventRecord(tm.e[1], s));
+      MCE_TRY_HIP(tm.record(1, s));
       MCE_TRY_HIP(hipMemcpyAsync(ctl, w.ctl.p, CTL_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       MCE_TRY_HIP(hipStreamSynchronize(s));
       j.hand_ms = tm.ms(0, 1);
@@ -346,8 +399,10 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
 
 namespace {
 
+// `noalloc`: every buffer comes from the active Carver (the caller installed
+// one), no events are created, and the launch uses smaller donation tables.
 int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_result* out, mce_clique_buf* cl,
-                const mce_per_vertex* pv, Workspace& ws) {
+                const mce_per_vertex* pv, Workspace& ws, bool noalloc = false) {
   hipStream_t s = (hipStream_t)opts.hip_stream;
   const uint64_t n = g->n;
   if (n >= 0xFFFFFFFFULL) {
@@ -378,7 +433,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   MCE_TRY(stage_csr(g, ws, s, &rp, &col, &nnz));
   if (n == 0) {
     if (pv && pv->size_hist && pv->hist_len)
-      MCE_TRY_HIP(hipMemsetAsync(pv->size_hist, 0, pv->hist_len * sizeof(uint64_t), s));
+      MCE_TRY_HIP(dev_zero(pv->size_hist, pv->hist_len * sizeof(uint64_t), s));
     if (cl) {
       cl->n_cliques = 0;
       cl->n_verts = 0;
@@ -394,8 +449,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   if (opts.validate) MCE_TRY(validate_csr(n, rp, col, ws, s));
 
   Timer tm;
-  MCE_TRY(tm.init());
-  MCE_TRY_HIP(hipEventRecord(tm.e[0], s));
+  MCE_TRY(tm.init(!noalloc));
+  MCE_TRY_HIP(tm.record(0, s));
 
   // --- rank (Section 4.2)
   MCE_TRY(ws.metric.ensure(n * sizeof(uint64_t)));
@@ -411,7 +466,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
       tri = ws.tri.as<uint64_t>();
     }
   }
-  MCE_TRY_HIP(hipEventRecord(tm.e[1], s));
+  MCE_TRY_HIP(tm.record(1, s));
 
   // --- subproblem sizes and build (Algorithm 4, body)
   MCE_TRY(ws.P.ensure(n * sizeof(uint32_t)));
@@ -442,9 +497,9 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     return MCE_EINVAL;
   }
 
-  MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
+  MCE_TRY_HIP(dev_zero(b.stats, 8 * sizeof(uint64_t), s));
   MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
-  MCE_TRY_HIP(hipMemsetAsync(b.xmark, 0, xwords * sizeof(uint32_t), s));
+  MCE_TRY_HIP(dev_zero(b.xmark, xwords * sizeof(uint32_t), s));
   MCE_TRY_HIP(launch_mark(n, rp, col, metric, b, s));
   MCE_TRY_HIP(launch_words(n, rp, b, s));
   MCE_TRY(device_exclusive_scan(b.words, ws.off.as<uint64_t>(), n, ws.scan_tmp, ws.scan_bytes, s));
@@ -466,7 +521,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   const uint64_t arena_words = tail[0] + tail[1], gid_words = tail[2] + tail[3];
   MCE_TRY(ws.arena.ensure(std::max<uint64_t>(arena_words, 1) * sizeof(uint64_t)));
   MCE_TRY(ws.gids.ensure(std::max<uint64_t>(gid_words, 1) * sizeof(uint32_t)));
-  MCE_TRY_HIP(hipMemsetAsync(ws.arena.p, 0, std::max<uint64_t>(arena_words, 1) * sizeof(uint64_t), s));
+  MCE_TRY_HIP(dev_zero(ws.arena.p, std::max<uint64_t>(arena_words, 1) * sizeof(uint64_t), s));
   MCE_TRY_HIP(launch_build(n, rp, col, metric, b, ws.off.as<uint64_t>(), ws.goff.as<uint64_t>(),
                            ws.arena.as<uint64_t>(), ws.gids.as<uint32_t>(), s));
 
@@ -492,7 +547,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
                                   ws.split_total.as<double>(), ws.split.as<uint32_t>(), s));
     split = ws.split.as<uint32_t>();
   }
-  MCE_TRY_HIP(hipEventRecord(tm.e[2], s));
+  MCE_TRY_HIP(tm.record(2, s));
 
   // --- clique output buffers
   uint64_t* cl_off = nullptr;
@@ -535,7 +590,14 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   job.cap_cliques = cl ? cl->cap_cliques : 0;
   job.cap_verts = cl ? cl->cap_verts : 0;
   job.opts = &opts;
-  if (!opts.inline_compact && nq >= (1u << 17)) {
+  if (noalloc) {
+    // modest tables that fit the scratch: 16 MiB of handoff records, 256
+    // donation blocks (2 MiB), 2^18 queue tickets (2 MiB)
+    job.hand_initial_units = (16ULL << 20) / 64;
+    job.pool_blocks = 256;
+    job.max_tickets = 1ULL << 18;
+    job.timing = false;
+  } else if (!opts.inline_compact && nq >= (1u << 17)) {
     // a large call cannot rely on the demand of earlier (maybe smaller) runs
     // to size the handoff arena: offer a quarter of the free device memory
     // (bounded by the arena's maximum; the buffer only grows)
@@ -543,10 +605,10 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) job.hand_initial_units = free_b / 4 / 64;
   }
   job.before_launch = [&](uint32_t attempt, uint64_t* ctl_dev) -> int {
-    if (hist) MCE_TRY_HIP(hipMemsetAsync(hist, 0, hist_len * sizeof(uint64_t), s));
+    if (hist) MCE_TRY_HIP(dev_zero(hist, hist_len * sizeof(uint64_t), s));
     if (attempt > 0) {
       // results of the aborted run are discarded: reset per-vertex outputs
-      MCE_TRY_HIP(hipMemsetAsync(b.stats, 0, 8 * sizeof(uint64_t), s));
+      MCE_TRY_HIP(dev_zero(b.stats, 8 * sizeof(uint64_t), s));
       MCE_TRY_HIP(launch_sizes(n, rp, col, metric, b, nodes_v, count_v, hash_v, s));
     }
     if (cl) {
@@ -558,7 +620,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   };
   uint64_t ctl[CTL_WORDS];
   MCE_TRY(run_enum(job, ws.ew, s, ctl, &out->retries));
-  MCE_TRY_HIP(hipEventRecord(tm.e[3], s));
+  MCE_TRY_HIP(tm.record(3, s));
   if (hist) {
     hipLaunchKernelGGL(k_hist_singletons, dim3(1), dim3(1), 0, s, hist, hist_len, b.stats);
     MCE_TRY_HIP(hipGetLastError());
@@ -602,6 +664,26 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   return rc;
 }
 
+// Scratch of the allocation-free entry point: one copy per GPU, held until the
+// process ends.  Host code reaches it only through the per-device address
+// from hipGetSymbolAddress (g_scratch), never through the array's name.
+static __device__ __align__(256) uint8_t scratch[MCE_NOALLOC_SCRATCH_BYTES];
+void* g_scratch[64];  // device address of `scratch` per device, set on first use (under g_mu)
+
+int scratch_of(int dev, void** out) {
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return MCE_EDEVICE;
+    }
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return MCE_OK;
+}
+
 }  // namespace
 }  // namespace mce
 
@@ -634,6 +716,24 @@ int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result
   MCE_TRY(current_device(&dev));
   std::lock_guard<std::mutex> lk(g_mu[dev]);
   return static_impl(g, rank, o, out, cliques, per_vertex, g_ws[dev]);
+}
+
+int mce_static_noalloc(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
+                       mce_clique_buf* cliques, const mce_per_vertex* per_vertex) {
+  if (!g || !out) {
+    set_error("NULL graph or result");
+    return MCE_EINVAL;
+  }
+  mce_opts o = opts ? *opts : default_opts();
+  int dev;
+  MCE_TRY(current_device(&dev));
+  std::lock_guard<std::mutex> lk(g_mu[dev]);
+  void* base;
+  MCE_TRY(scratch_of(dev, &base));
+  Carver c{(uint8_t*)base, MCE_NOALLOC_SCRATCH_BYTES, 0};
+  CarverScope scope(&c);
+  Workspace ws;  // every buffer of this call is carved from the scratch
+  return static_impl(g, rank, o, out, cliques, per_vertex, ws, true);
 }
 
 int mce_rank_metric(const mce_csr* g, mce_rank rank, uint64_t* metric, void* hip_stream) {

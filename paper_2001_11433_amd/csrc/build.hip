@@ -339,7 +339,7 @@ hipError_t launch_queue_fill(uint64_t nq, const uint32_t* vals, const uint32_t* 
 hipError_t launch_split_plan(uint64_t n, const uint32_t* p, const float* cost, uint32_t waves, uint32_t split_max,
                              double* total, uint32_t* split, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(total, 0, sizeof(double), s);
+  hipError_t e = dev_zero(total, sizeof(double), s);
   if (e != hipSuccess) return e;
   const uint32_t blocks = std::min<uint32_t>(blocks_for(n, 256), 1024);
   hipLaunchKernelGGL(k_split_total, dim3(blocks), dim3(256), 0, s, n, p, cost, total);
@@ -352,13 +352,7 @@ int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& 
                           hipStream_t s) {
   size_t need = 0;
   MCE_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s));
-  if (need > tmp_bytes) {
-    if (tmp) MCE_TRY_HIP(hipFree(tmp));
-    tmp = nullptr;
-    tmp_bytes = 0;
-    MCE_TRY_HIP(hipMalloc(&tmp, need));
-    tmp_bytes = need;
-  }
+  MCE_TRY(ensure_temp(tmp, tmp_bytes, need));
   MCE_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, need, in, out, (int)n, s));
   return MCE_OK;
 }
@@ -369,13 +363,7 @@ int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_
   hipcub::DoubleBuffer<uint32_t> vb(vals, vals_alt);
   size_t need = 0;
   MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, need, kb, vb, (int)n, 0, end_bit, s));
-  if (need > tmp_bytes) {
-    if (tmp) MCE_TRY_HIP(hipFree(tmp));
-    tmp = nullptr;
-    tmp_bytes = 0;
-    MCE_TRY_HIP(hipMalloc(&tmp, need));
-    tmp_bytes = need;
-  }
+  MCE_TRY(ensure_temp(tmp, tmp_bytes, need));
   MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, need, kb, vb, (int)n, 0, end_bit, s));
   *keys_out = kb.Current();
   *vals_out = vb.Current();

@@ -114,16 +114,51 @@ constexpr uint32_t kHistLds = 64;
 // A node is handed off only when its K list has at most kHandK vertices.
 constexpr uint32_t kHandK = 64;
 
+// Bump allocator over a fixed device region (the scratch array of the
+// allocation-free entry point).  While one is installed on the calling thread
+// (CarverScope), DevBuf::ensure and the temp-storage helpers take their memory
+// from it instead of calling hipMalloc; nothing taken is ever freed.
+struct Carver {
+  uint8_t* base;
+  uint64_t cap, used;
+  void* take(uint64_t b) {
+    const uint64_t at = (used + 255) & ~255ULL;
+    if (at > cap || b > cap - at) return nullptr;
+    used = at + b;
+    return base + at;
+  }
+};
+Carver*& active_carver();  // the calling thread's, or null
+struct CarverScope {
+  Carver* prev;
+  explicit CarverScope(Carver* c) : prev(active_carver()) { active_carver() = c; }
+  ~CarverScope() { active_carver() = prev; }
+};
+// Takes `b` bytes from the active carver (MCE_ENOTSUP with a message when the
+// scratch is exhausted).
+int carve(void** p, uint64_t b);
+
 // Grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool carved = false;  // taken from a Carver: never freed
   int ensure(size_t b) {
     if (b <= bytes && p) return MCE_OK;
+    if (active_carver()) {
+      void* q = nullptr;
+      int rc = carve(&q, std::max<size_t>(b, 256));
+      if (rc != MCE_OK) return rc;
+      p = q;
+      bytes = std::max<size_t>(b, 256);
+      carved = true;
+      return MCE_OK;
+    }
     if (p) {
-      (void)hipFree(p);
+      if (!carved) (void)hipFree(p);
       p = nullptr;
       bytes = 0;
+      carved = false;
     }
     size_t want = std::max<size_t>(b, 256);
     hipError_t e = hipMalloc(&p, want);
@@ -137,9 +172,10 @@ struct DevBuf {
     return MCE_OK;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !carved) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    carved = false;
   }
   template <class T>
   T* as() const {
@@ -188,6 +224,10 @@ struct EnumJob {
   // initial handoff arena in 64-byte units when no earlier run sized it
   // (0 = a small default)
   uint64_t hand_initial_units = 0;
+  // donation pool blocks and queue tickets (0 = the defaults: 2^16 blocks of
+  // 8 KiB, max(2^24, 4 * nq) tickets)
+  uint64_t pool_blocks = 0, max_tickets = 0;
+  bool timing = true;  // device-time events around the compact launch
   // written by run_enum: compact-kernel time and the nodes handed to it
   double hand_ms = 0;
   uint64_t handed = 0;
@@ -247,6 +287,11 @@ hipError_t launch_split_plan(uint64_t n, const uint32_t* p, const float* cost, u
                              double* total, uint32_t* split, hipStream_t s);
 int device_exclusive_scan(const uint64_t* in, uint64_t* out, uint64_t n, void*& tmp, size_t& tmp_bytes,
                           hipStream_t s);
+// Temp storage of at least `need` bytes in (tmp, tmp_bytes): carved while a
+// Carver is active, else grown with hipMalloc.
+int ensure_temp(void*& tmp, size_t& tmp_bytes, size_t need);
+// Zero `bytes` (a multiple of 4) at p with a fill kernel.
+hipError_t dev_zero(void* p, uint64_t bytes, hipStream_t s);
 int device_sort_desc(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint64_t n,
                      void*& tmp, size_t& tmp_bytes, hipStream_t s, uint64_t** keys_out, uint32_t** vals_out,
                      int end_bit = 64);

@@ -225,7 +225,7 @@ hipError_t launch_degree(uint64_t n, const uint64_t* rp, uint64_t* metric, hipSt
 hipError_t launch_root_metric(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* metric, uint64_t* best,
                               hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(best, 0, sizeof(uint64_t), s);
+  hipError_t e = dev_zero(best, sizeof(uint64_t), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_root_pivot, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, best);
   hipLaunchKernelGGL(k_root_metric_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, metric);
@@ -275,7 +275,7 @@ int run_peel_rounds(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_
 
 hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col, uint64_t* tri, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(tri, 0, n * sizeof(uint64_t), s);
+  hipError_t e = dev_zero(tri, n * sizeof(uint64_t), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_triangles, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, tri);
   return hipGetLastError();
