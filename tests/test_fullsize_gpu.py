@@ -8,10 +8,15 @@ The oracle cannot enumerate these graphs whole in test time, so:
     vertices; totals against the sums of the per-subproblem triples;
   * R-MAT scale 18: rank metrics (degree, core number, triangles) of every
     vertex against the oracle (its enumeration is far beyond reach);
-  * the 500k-vertex Chung-Lu stream: sampled new and subsumed cliques checked
-    against the definition of the two sets, and the running count and hash
-    against a fresh enumeration of the updated graph.
+  * the 500k-vertex Chung-Lu stream: all eight result fields of all 200
+    batches against the oracle's sequential IMCE (stored by
+    oracle/make_golden.py in tests/golden/c5_stream.json); sampled new and
+    subsumed cliques of the first batches against the definition of the two
+    sets, and the running count and hash against a fresh enumeration.
 """
+
+import json
+import os
 
 import numpy as np
 import pytest
@@ -20,6 +25,7 @@ import graphgen as gg
 import oracle as O
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -113,4 +119,24 @@ def test_cl500k_stream_sampled_cliques_and_recompute(m):
         full = m.mce_static(new_g, rank="degree", **kw)
         assert (full["count"], full["set_hash"]) == (r["count"], r["set_hash"]), b
         cur = new_g
+    st.close()
+
+
+def test_cl500k_stream_every_batch_equals_the_oracle(m):
+    # the benchmark's stream in the benchmark's tuned incremental launch: every
+    # batch's (applied, skipped, |new|, |subsumed|, H(new), H(subsumed), count,
+    # set hash) equals the oracle's, and so does the initial enumeration
+    from paper_2001_11433_amd import tuner
+    with open(os.path.join(GOLDEN, "c5_stream.json")) as f:
+        gold = json.load(f)
+    g = gg.chung_lu(500_000, 2.2, 16, seed=0)
+    stream = gg.edge_stream(g, 200, 1000, 5000, seed=2, triadic_fraction=0.5)
+    kw = tuner.launch_kwargs(tuner.lookup_imce(g, family="cl500k"))
+    st = m.ImceState(g, **kw)
+    assert (st.initial["count"], "%016x" % st.initial["set_hash"]) == (gold["initial"]["count"],
+                                                                         gold["initial"]["set_hash"])
+    for b, (src, dst) in enumerate(stream):
+        r = st.add(src, dst)
+        got = [r[k] if not k.startswith("hash") and k != "set_hash" else "%016x" % r[k] for k in gold["fields"]]
+        assert got == gold["batches"][b], (b, got, gold["batches"][b])
     st.close()
