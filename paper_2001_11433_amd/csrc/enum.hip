@@ -42,8 +42,8 @@ constexpr uint32_t kCFrames = 66;     // compact depth <= 64 below the re-based 
 
 // pool record layout (64-bit words)
 enum { R_S = 0, R_TYPE = 1, R_DEPTH = 2, R_KLEN = 3, R_HDR = 4 };
-// compact record: frame at [4, 10), then rows and tables
-constexpr uint32_t kCR_PP = 10, kCR_XP = 74, kCR_PX = 138, kCR_EX = 202, kCR_KEY = 266, kCR_GP = 330, kCR_K = 362;
+// compact record: a frame (kCF words) at R_HDR, then rows and tables
+constexpr uint32_t kCR_PP = 12, kCR_XP = 76, kCR_PX = 140, kCR_EX = 204, kCR_KEY = 268, kCR_GP = 332, kCR_K = 364;
 
 struct Lds {
   uint64_t sP[64];
@@ -408,135 +408,192 @@ __device__ __forceinline__ uint32_t vbcnt_add(uint64_t x, uint32_t acc) {
   return r;
 }
 
+// Tallies of the compact search.  Counts decided for the whole wave (nodes,
+// cliques, op terms of a node or of a set of children given as a lane mask)
+// are scalar; the clique-hash terms and the op terms of single-candidate
+// children are summed per lane (each lane adds the children it decides) and
+// reduced over the wave once per task.
 struct VTally {
-  uint64_t vz;  // opaque zero
-  uint64_t tn, tc, th, ss, es;
-  __device__ void node() { tn += 1; }
-  __device__ void clique(uint64_t zsum, uint32_t k) {
-    tc += 1;
-    th += clique_term(zsum + vz, k);
+  uint64_t tn, tc, ss, es;  // scalar
+  uint64_t vh, vss;         // per lane
+  __device__ void init() {
+    tn = tc = ss = es = 0;
+    vh = vss = 0;
   }
   __device__ void flush(Acc& acc) const {
-    acc.tn += readlane64(tn, 0);
-    acc.tc += readlane64(tc, 0);
-    acc.th += readlane64(th, 0);
-    acc.ssum += readlane64(ss, 0);
-    acc.esum += readlane64(es, 0);
+    acc.tn += tn;
+    acc.tc += tc;
+    acc.th += wave_sum_u64(vh);
+    acc.ssum += ss + wave_sum_u64(vss);
+    acc.esum += es;
   }
 };
 
-// BIGK: the K list lives in the wave's global region `gK` instead of LDS
-// (subproblems whose cliques can reach the LDS list's length).
+// 64-bit value of lane `src` (per lane) through the LDS crossbar; every lane
+// must be active.
+__device__ __forceinline__ uint64_t bpermute64(uint64_t v, uint32_t src) {
+  const int addr = (int)(src << 2);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// v in the lanes whose bit is set in the lane mask `lanes` (a wave-uniform
+// 64-bit value), 0 in the others: one select with the mask as its condition.
+__device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
+  // the mask is wave-uniform; readfirstlane states that to the compiler so it
+  // sits in a scalar register pair (free when it already does)
+  const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(lanes >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)lanes);
+  uint32_t r;
+  asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(m));
+  return r;
+}
+
+// Frame of a compact node with deep children still to visit (kCF words):
+//   0 cand P   1 fini from cand Xp   2 fini from the root fini Xx   3 ext
+//   4 zsum     5 excluded-edge mask F  6 |K|                       7 D
+// where D = the deep children (two or more candidates) not yet visited.  A
+// child q's (cand, fini) follow from the node's by Algorithm 3's formula:
+// cand = (P \ ext_{<q}) n Gamma(q), fini = (Xp u ext_{<q}) n Gamma(q) plus
+// Xx n Gamma(q), with ext_{<q} the children before q (ascending).
+//
+// Expanding a node (Algorithm 1): the pivot by a wave max over (t_u, id),
+// ext = P \ Gamma(pivot), then ONE vector pass over the children: lane q
+// (q in ext) forms its child's cand and fini and decides it at once when the
+// child's cand is empty (a leaf: one node, a clique iff its fini is empty) or
+// holds one vertex w (one node; the grandchild K+q+w is a second node and a
+// clique unless a fini vertex is adjacent to w, which then is the pivot with
+// ext empty, or the branch on w is excluded).  The remaining "deep" children
+// are visited in ascending order by descending into them.  The recursion
+// tree, and with it every count, is the sequential one.
+//
+// Entry: expand = true starts at the node (P, Xp, Xx) itself; expand = false
+// resumes a node whose deep children D are left (a donated record).
 template <bool EXCL, bool BIGK, class LT>
 __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
-                            uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t F, uint64_t zsum, bool expand,
-                            uint32_t kbase, uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since,
+                            uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t D, uint64_t F, uint64_t zsum,
+                            bool expand, uint32_t kbase, uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since,
                             const WideCtx* wide, Diag& dg) {
   const int lane = lane_id();
   uint32_t* const kG = BIGK ? gK : L.kG;
-  uint32_t d = 0;       // frames on the stack
-  uint32_t kl = kbase;  // |K| of the current node (a last child reuses its parent's frame slot)
+  uint32_t d = 0;       // frames on the stack (each with deep children left)
+  uint32_t kl = kbase;  // |K| of the current node
+  bool framed = false;  // the current node's frame is the top of the stack
   const uint64_t t0 = now();
   const uint32_t dlim = 4 * a.donate_interval;
+  const uint64_t lower = (1ULL << lane) - 1;  // the children before this lane's
   VTally T;
-  T.vz = opaque_vzero64();
-  T.tn = T.tc = T.th = T.ss = T.es = T.vz;
+  T.init();
   for (;;) {
     if (expand) {
       expand = false;
-      T.node();
+      framed = false;
+      T.tn += 1;
+      D = 0;
       if (P == 0) {
+        // only a task's first node can arrive here with an empty cand
         if ((Xp | Xx) == 0) {
-          T.clique(zsum, kl);
+          T.tc += 1;
+          if (lane == 0) T.vh += clique_term(zsum, kl);
           if (a.emit_extra) {
             if (a.cl_vert) store_clique(a, kl, kG);
             if (a.hist) hist_add(a, L.hist, kl);
           }
         }
-        ext = 0;  // no children: the node is done
       } else {
-        const uint64_t mP = P | Xp;
-        const uint32_t k1 = ((mP >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP) : 0u;
-        const uint32_t k2 = ((Xx >> lane) & 1ULL) ? (((uint32_t)__popcll(P & c.rowXP) << 16) | c.keyX) : 0u;
+        // pivot: largest |P n Gamma(u)| over u in P u X, smallest id on ties
+        const uint32_t k1 = lanes_select(P | Xp, ((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP);
+        const uint32_t k2 = lanes_select(Xx, ((uint32_t)__popcll(P & c.rowXP) << 16) | c.keyX);
         const uint32_t mx = wave_max_u32(k1 > k2 ? k1 : k2);
         const uint32_t row = mx & 0xFFu;
-        uint64_t prow;  // the pivot's row over the cand columns (a cand or a fini row)
-        if (row < 64)
-          prow = readlane64(c.rowPP, row);
-        else
-          prow = readlane64(c.rowXP, row & 63);
+        const uint64_t prow = row < 64 ? readlane64(c.rowPP, row) : readlane64(c.rowXP, row & 63);
         ext = P & ~prow;
-        T.ss += vbcnt_add(Xx, vbcnt_add(Xp, vbcnt_add(P, (uint32_t)T.vz)));
-        T.es += vbcnt_add(ext, (uint32_t)T.vz);
+        T.ss += (uint64_t)(__popcll(P) + __popcll(Xp) + __popcll(Xx));
+        T.es += (uint64_t)__popcll(ext);
+        // the child pass: lane q forms child q's cand and fini; the lane masks
+        // of the children that are leaves or have one candidate decide them
+        const uint64_t chm = EXCL ? (ext & ~F) : ext;  // excluded q join fini unvisited
+        const uint64_t below = ext & lower;
+        const uint64_t cP = (P & ~below) & c.rowPP;
+        const uint64_t cXp = (Xp | below) & c.rowPP;
+        const uint64_t cXx = Xx & c.rowPX;
+        const uint32_t pc = (uint32_t)__popcll(cP);
+        const uint64_t zm = ballot(pc == 0);
+        const uint64_t om = ballot(pc == 1);
+        const uint64_t fm = ballot((cXp | cXx) == 0);
+        const uint64_t leafm = chm & zm;
+        const uint64_t onem = chm & om;
+        D = chm & ~(zm | om);
+        uint64_t cliqm = leafm & fm;
+        uint64_t grandm = 0;
+        uint32_t w = 0;
+        T.tn += (uint64_t)(__popcll(leafm) + __popcll(onem));
+        if (onem) {
+          // one candidate w: the child is one node; if no fini vertex is
+          // adjacent to w (then the pivot, with ext empty) and the branch on w
+          // is not excluded, the grandchild K+q+w is a second node and a clique
+          w = pc ? (uint32_t)__builtin_ctzll(cP) : 0u;
+          const uint64_t rw = bpermute64(c.rowPP, w);
+          const uint64_t rwx = bpermute64(c.rowPX, w);
+          const uint64_t blk = ballot(((cXp & rw) | (cXx & rwx)) != 0);
+          uint64_t ok = onem & ~blk;
+          if (EXCL) ok &= ~ballot((((F | c.rowEx) >> w) & 1ULL) != 0);
+          grandm = ok;
+          cliqm |= grandm;
+          T.tn += (uint64_t)__popcll(grandm);
+          T.es += (uint64_t)__popcll(onem & ~blk);
+          // the child's pivot step, counted like an expanded node's
+          if ((onem >> lane) & 1ULL) T.vss += 1u + (uint32_t)__popcll(cXp) + (uint32_t)__popcll(cXx);
+        }
+        if (cliqm) {
+          T.tc += (uint64_t)__popcll(cliqm);
+          const uint64_t zw = grandm ? bpermute64(c.zP, w) : 0ULL;
+          if ((cliqm >> lane) & 1ULL) {
+            const bool two = (grandm >> lane) & 1ULL;
+            T.vh += clique_term(zsum + c.zP + (two ? zw : 0ULL), kl + (two ? 2u : 1u));
+          }
+          if (a.emit_extra) {
+            uint64_t cm = cliqm;
+            while (cm) {
+              const uint32_t q = (uint32_t)__builtin_ctzll(cm);
+              cm &= cm - 1;
+              const bool two = (grandm >> q) & 1ULL;
+              if (a.cl_vert) {
+                if (lane == 0) {
+                  kG[kl] = readlane32(c.gP, q);
+                  if (two) kG[kl + 1] = readlane32(c.gP, readlane32(w, q));
+                }
+                __syncthreads();  // the K list is read by every lane
+                store_clique(a, kl + (two ? 2u : 1u), kG);
+              }
+              if (a.hist) hist_add(a, L.hist, kl + (two ? 2u : 1u));
+            }
+          }
+        }
       }
     }
-    while (ext) {
-      const uint32_t q = (uint32_t)__builtin_ctzll(ext);
-      const uint64_t qb = 1ULL << q;
-      ext &= ~qb;
-      if (EXCL && (F & qb)) {
-        // K u {q} would contain an excluded edge: q moves to fini unvisited
-        P &= ~qb;
-        Xp |= qb;
-        continue;
-      }
-      const uint64_t rq = readlane64(c.rowPP, q);
-      const uint64_t rqx = readlane64(c.rowPX, q);
-      P &= ~qb;
-      Xp |= qb;
-      const uint64_t cP = P & rq;
-      if (cP == 0) {
-        // the child is a leaf (its cand is empty): one node, maximal iff its
-        // fini is empty too; no frame needed
-        T.node();
-        if (((Xp & rq) | (Xx & rqx)) == 0) {
-          T.clique(zsum + readlane64(c.zP, q), kl + 1);
-          if (a.emit_extra) {
-            if (a.cl_vert) {
-              if (lane == 0) kG[kl] = readlane32(c.gP, q);
-              __syncthreads();  // the K list is read by every lane
-              store_clique(a, kl + 1, kG);
-            }
-            if (a.hist) hist_add(a, L.hist, kl + 1);
-          }
-        }
-        continue;
-      }
-      if (__popcll(cP) == 1) {
-        // the child has one candidate w.  Every t_u of the child is 0 or 1:
-        // if a fini vertex is adjacent to w it is the pivot and ext is empty
-        // (one node); else ext = {w} and the grandchild K+q+w has empty cand
-        // and fini (two nodes, one clique), unless the branch on w is
-        // excluded by an earlier batch edge
-        const uint32_t w = (uint32_t)__builtin_ctzll(cP);
-        const uint64_t rw = readlane64(c.rowPP, w), rwx = readlane64(c.rowPX, w);
-        const uint64_t cXp = Xp & rq, cXx = Xx & rqx;
-        T.node();
-        const bool blocked = ((cXp & rw) | (cXx & rwx)) != 0;
-        const bool excluded = EXCL && (((F | readlane64(c.rowEx, q)) >> w) & 1ULL);
-        // the child's pivot step, as the op count of an expanded node
-        T.ss += vbcnt_add(cXx, vbcnt_add(cXp, (uint32_t)T.vz + 1u));
-        if (!blocked) T.es += 1;
-        if (!blocked && !excluded) {
-          T.node();
-          T.clique(zsum + readlane64(c.zP, q) + readlane64(c.zP, w), kl + 2);
-          if (a.emit_extra) {
-            if (a.cl_vert) {
-              if (lane == 0) {
-                kG[kl] = readlane32(c.gP, q);
-                kG[kl + 1] = readlane32(c.gP, w);
-              }
-              __syncthreads();  // the K list is read by every lane
-              store_clique(a, kl + 2, kG);
-            }
-            if (a.hist) hist_add(a, L.hist, kl + 2);
-          }
-        }
-        continue;
-      }
-      if (ext) {
-        // other children follow: save this node (one lane stores the uniform
-        // frame words).  The last child takes the node's place instead.
+    if (D == 0) {
+      // resume the nearest ancestor with deep children left
+      if (d == 0) break;
+      const uint64_t v = lane < (int)kCF ? L.cstk[(d - 1) * kCF + lane] : 0;
+      P = readlane64(v, 0);
+      Xp = readlane64(v, 1);
+      Xx = readlane64(v, 2);
+      ext = readlane64(v, 3);
+      zsum = readlane64(v, 4);
+      if (EXCL) F = readlane64(v, 5);
+      kl = readlane32((uint32_t)v, 6);
+      D = readlane64(v, 7);
+      framed = true;
+    }
+    // descend into the lowest deep child q
+    const uint32_t q = (uint32_t)__builtin_ctzll(D);
+    D &= D - 1;
+    if (D) {
+      if (framed) {
+        if (lane == 0) L.cstk[(d - 1) * kCF + 7] = D;
+      } else {
         if (lane == 0) {
           uint64_t* f = &L.cstk[d * kCF];
           f[0] = P;
@@ -546,93 +603,75 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
           f[4] = zsum;
           f[5] = EXCL ? F : 0;
           f[6] = kl;
+          f[7] = D;
         }
         ++d;
       }
-      if (lane == 0) kG[kl] = readlane32(c.gP, q);
-      ++kl;
-      P = cP;
-      Xp &= rq;
-      Xx &= rqx;
-      if (EXCL) F |= readlane64(c.rowEx, q);
-      zsum += readlane64(c.zP, q);
-      expand = true;
+    } else if (framed) {
+      --d;  // its last deep child: the frame's slot is free
+    }
+    const uint64_t below = ext & ((1ULL << q) - 1);
+    const uint64_t rq = readlane64(c.rowPP, q);
+    const uint64_t rqx = readlane64(c.rowPX, q);
+    if (lane == 0) kG[kl] = readlane32(c.gP, q);
+    ++kl;
+    Xp = (Xp | below) & rq;
+    P = (P & ~below) & rq;
+    Xx &= rqx;
+    if (EXCL) F |= readlane64(c.rowEx, q);
+    zsum += readlane64(c.zP, q);
+    expand = true;
 
-      if (can_donate && ++since >= dlim) {
-        since = 0;
-        const uint64_t td = now();
-        for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
-          ++dg.attempts;
-          if constexpr (sizeof(LT) == sizeof(Lds)) {
-            if (wide && donate_wide(a, L, *wide, can_donate)) continue;
-          }
-          uint32_t i = 0;
-          uint64_t e = 0;
-          for (; i < d; ++i) {
-            e = L.cstk[i * kCF + 3];
-            if (e) break;
-          }
-          const uint32_t klen = (uint32_t)L.cstk[i * kCF + 6];
-          if (i < d && kCR_K + (klen + 1) / 2 <= kBlockWords) {
-            const uint32_t keep = (uint32_t)__popcll(e) / 2;
-            uint64_t don = e;
-            for (uint32_t z = 0; z < keep; ++z) don &= don - 1;
-            const uint64_t km = e & ~don;  // the lowest `keep` children stay here
-            const uint32_t blk = reserve_record(a, can_donate);
-            if (blk != kNil) {
-              uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
-              if (lane == 0) {
-                rec[R_S] = s;
-                rec[R_TYPE] = 1;
-                rec[R_DEPTH] = c.np | (c.nx << 8);
-                rec[R_KLEN] = klen;
-              }
-              if (lane < 6) {
-                uint64_t v = L.cstk[i * kCF + lane];
-                if (lane == 0) v &= ~km;
-                if (lane == 1) v |= km;
-                if (lane == 3) v = don;
-                rec[R_HDR + lane] = v;
-              }
-              rec[kCR_PP + lane] = c.rowPP;
-              rec[kCR_XP + lane] = c.rowXP;
-              rec[kCR_PX + lane] = c.rowPX;
-              if (EXCL) rec[kCR_EX + lane] = c.rowEx;
-              rec[kCR_KEY + lane] = (uint64_t)c.keyP | ((uint64_t)c.keyX << 32);
-              ((uint32_t*)(rec + kCR_GP))[lane] = c.gP;
-              if (BIGK) __syncthreads();  // K entries written by single lanes in global memory
-              for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = kG[j];
-              if (lane == 0) L.cstk[i * kCF + 3] = km;
-              publish_record(a, blk);
-            } else {
-              break;
-            }
-          } else {
-            break;
-          }
+    if (can_donate && ++since >= dlim) {
+      since = 0;
+      const uint64_t td = now();
+      for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
+        ++dg.attempts;
+        if constexpr (sizeof(LT) == sizeof(Lds)) {
+          if (wide && donate_wide(a, L, *wide, can_donate)) continue;
         }
-        dg.t_donate += now() - td;
+        // the shallowest frame with two or more deep children left gives away
+        // the upper half of them (it keeps at least one, so it stays a frame)
+        uint32_t i = 0;
+        uint64_t e = 0;
+        for (; i < d; ++i) {
+          e = L.cstk[i * kCF + 7];
+          if (__popcll(e) >= 2) break;
+        }
+        if (i >= d) break;
+        const uint32_t klen = (uint32_t)L.cstk[i * kCF + 6];
+        if (kCR_K + (klen + 1) / 2 > kBlockWords) break;
+        const uint32_t keep = (uint32_t)__popcll(e) / 2;
+        uint64_t don = e;
+        for (uint32_t z = 0; z < keep; ++z) don &= don - 1;
+        const uint64_t km = e & ~don;  // the lowest `keep` deep children stay here
+        const uint32_t blk = reserve_record(a, can_donate);
+        if (blk == kNil) break;
+        uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
+        if (lane == 0) {
+          rec[R_S] = s;
+          rec[R_TYPE] = 1;
+          rec[R_DEPTH] = c.np | (c.nx << 8);
+          rec[R_KLEN] = klen;
+        }
+        if (lane < (int)kCF) rec[R_HDR + lane] = lane == 7 ? don : L.cstk[i * kCF + lane];
+        rec[kCR_PP + lane] = c.rowPP;
+        rec[kCR_XP + lane] = c.rowXP;
+        rec[kCR_PX + lane] = c.rowPX;
+        if (EXCL) rec[kCR_EX + lane] = c.rowEx;
+        rec[kCR_KEY + lane] = (uint64_t)c.keyP | ((uint64_t)c.keyX << 32);
+        ((uint32_t*)(rec + kCR_GP))[lane] = c.gP;
+        if (BIGK) __syncthreads();  // K entries written by single lanes in global memory
+        for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = kG[j];
+        if (lane == 0) L.cstk[i * kCF + 7] = km;
+        publish_record(a, blk);
       }
-      break;  // descend into the child
+      dg.t_donate += now() - td;
     }
-    if (expand) continue;
-    // pop
-    if (d == 0) {
-      dg.cnodes += readlane64(T.tn, 0);
-      T.flush(acc);
-      dg.t_compact += now() - t0;
-      return;
-    }
-    --d;
-    const uint64_t v = lane < 7 ? L.cstk[d * kCF + lane] : 0;
-    P = readlane64(v, 0);
-    Xp = readlane64(v, 1);
-    Xx = readlane64(v, 2);
-    ext = readlane64(v, 3);
-    zsum = readlane64(v, 4);
-    if (EXCL) F = readlane64(v, 5);
-    kl = readlane32((uint32_t)v, 6);
   }
+  dg.cnodes += T.tn;
+  T.flush(acc);
+  dg.t_compact += now() - t0;
 }
 
 // Tie-break keys: rank of each compact row's vertex id among all compact rows
@@ -661,7 +700,8 @@ __device__ void compact_keys(Compact& c) {
 
 template <bool EXCL>
 __device__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* kG, uint64_t& P, uint64_t& Xp,
-                                    uint64_t& Xx, uint64_t& ext, uint64_t& zsum, uint64_t& F, uint32_t& klen) {
+                                    uint64_t& Xx, uint64_t& ext, uint64_t& D, uint64_t& zsum, uint64_t& F,
+                                    uint32_t& klen) {
   const int lane = lane_id();
   const uint64_t hdr = readlane64(rec[R_DEPTH], 0);
   c.np = (uint32_t)(hdr & 0xFF);
@@ -677,13 +717,14 @@ __device__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* k
   c.gP = ((const uint32_t*)(rec + kCR_GP))[lane];
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
   for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
-  const uint64_t v = lane < 6 ? rec[R_HDR + lane] : 0;
+  const uint64_t v = lane < (int)kCF ? rec[R_HDR + lane] : 0;
   P = readlane64(v, 0);
   Xp = readlane64(v, 1);
   Xx = readlane64(v, 2);
   ext = readlane64(v, 3);
   zsum = readlane64(v, 4);
   F = readlane64(v, 5);
+  D = readlane64(v, 7);
 }
 
 // Handoff records (one per re-based node, for the compact kernel, which
@@ -816,17 +857,17 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     if (rtype == 1) {
       // donated compact subtree
       Compact c;
-      uint64_t P, Xp, Xx, ext, zsum, F;
+      uint64_t P, Xp, Xx, ext, D, zsum, F;
       uint32_t klen;
-      compact_from_record<EXCL>(rec, c, kG, P, Xp, Xx, ext, zsum, F, klen);
+      compact_from_record<EXCL>(rec, c, kG, P, Xp, Xx, ext, D, zsum, F, klen);
       __syncthreads();
       if (lane == 0) pool_push(a, blk);
       if (bigk)
-        compact_dfs<EXCL, true>(a, L, gK, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since,
-                                nullptr, dg);
+        compact_dfs<EXCL, true>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, acc, can_donate,
+                                since, nullptr, dg);
       else
-        compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, F, zsum, false, klen, wv, acc, can_donate, since,
-                                 nullptr, dg);
+        compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, acc, can_donate,
+                                 since, nullptr, dg);
     } else {
       const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
       const uint32_t F = 3 * wp + wf + wx + 1;
@@ -1037,10 +1078,10 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
                   const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
                   dg.t_rebase += now() - tr;
                   if (bigk)
-                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, acc,
                                             can_donate, since, &wctx, dg);
                   else
-                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, acc,
                                              can_donate, since, &wctx, dg);
                 }
                 rebased = true;
@@ -1200,13 +1241,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     const uint64_t idx = ref & 0xFFFFFFFFULL;
     Acc acc = {0, 0, 0, 0, 0};
     Compact c;
-    uint64_t P, Xp = 0, Xx, ext = 0, zsum, F;
+    uint64_t P, Xp = 0, Xx, ext = 0, D = 0, zsum, F;
     uint32_t klen, s;
     if (pooled) {
       // a donation among the compact kernel's own waves
       const uint64_t* rec = a.pool + idx * kBlockWords;
       s = (uint32_t)readlane64(rec[R_S], 0);
-      compact_from_record<EXCL>(rec, c, L.kG, P, Xp, Xx, ext, zsum, F, klen);
+      compact_from_record<EXCL>(rec, c, L.kG, P, Xp, Xx, ext, D, zsum, F, klen);
       __threadfence_block();
       if (lane == 0) pool_push(a, (uint32_t)idx);
     } else {
@@ -1217,7 +1258,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;
-    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, F, zsum, !pooled, klen, wv, acc, can_donate,
+    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, D, F, zsum, !pooled, klen, wv, acc, can_donate,
                              since, (const WideCtx*)nullptr, dg);
     if (lane == 0) {
       if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
