@@ -53,6 +53,7 @@ extern "C" {
 #define MCE_ENOSPC (-3)  /* a caller clique buffer is too small; required sizes written back */
 #define MCE_EDEVICE (-4) /* HIP runtime error */
 #define MCE_ENOTSUP (-5) /* input outside the supported envelope (see mce_static) */
+#define MCE_ECANCELED (-6) /* a submitted batch was dropped because an earlier one failed (imce_submit) */
 
 typedef struct {
   uint64_t n;               /* number of vertices */
@@ -147,6 +148,11 @@ typedef struct {
   uint64_t diag[8];
   double compact_ms;    /* device time of the compact kernel (included in enum_ms) */
   uint64_t handed;      /* re-based nodes it searched (the rest were searched in place) */
+  uint64_t exec_ops;    /* alg_ops at the row width the kernels execute: w = 2 * ceil(|cand|/64)
+                           of the subproblem for a wide node, w = 2 for a node re-based onto the
+                           compact 64 + 64 universe */
+  uint64_t lds_bytes;   /* algorithmic LDS bytes of the search: per node 4 * w * (s + |ext|), w
+                           and s as in alg_ops (the compact kernel keeps its rows in registers) */
 } mce_result;
 
 /* Clique output in CSR form: clique i is vert[off[i] .. off[i+1]), vertices
@@ -260,6 +266,35 @@ int imce_add_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uin
  * commit as imce_add_edges. */
 int imce_remove_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
                       imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
+
+/* Pipelined updates: the subsumed-clique pass of one batch (Algorithm 7) runs
+ * on the device while the next batch's new-clique search (Algorithms 5 and 8)
+ * runs, which is what a stream of batches of one session can overlap.
+ * imce_submit runs a batch's canonicalisation, the graph update and the
+ * new-clique search, starts its subsumed pass on a second stream of the state
+ * and returns; remove != 0 makes it a deletion batch (as imce_remove_edges).
+ * imce_collect waits for the oldest submitted batch and returns its result and
+ * cliques exactly as imce_add_edges / imce_remove_edges would have.  At most
+ * two submitted batches may be uncollected (else MCE_EINVAL); imce_add_edges
+ * and imce_remove_edges are refused (MCE_EINVAL) while any is.  Errors:
+ *   - imce_submit fails like imce_add_edges's first steps and then leaves the
+ *     state and the pending batch untouched;
+ *   - a failed subsumed pass is returned by imce_collect of that batch; the
+ *     graph, count and hash go back to before that batch, and a batch
+ *     submitted after it is dropped (its imce_submit returns MCE_ECANCELED);
+ *   - MCE_ENOSPC from imce_collect (caller buffers too small, sizes written
+ *     back) keeps the batch to be collected again; the batch is applied.
+ * The calls of one state must not overlap (one caller thread at a time). */
+int imce_submit(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device, int remove);
+int imce_collect(imce_state* st, imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl);
+
+/* Device memory the state holds now (graph buffers, work buffers, tables),
+ * and an estimate of what a batch of rho edges may add to it (from the
+ * library's own sizing rules; the edge-subproblem rows at the largest bytes
+ * per edge seen so far), in bytes: what the admission decision of a serving
+ * loop budgets. */
+int imce_device_bytes(const imce_state* st, uint64_t* bytes);
+int imce_batch_bytes(const imce_state* st, uint64_t rho, uint64_t* bytes);
 
 /* Current graph: n and the number of stored adjacency entries (2m). */
 int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash);

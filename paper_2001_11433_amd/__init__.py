@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmce.so")
 
-MCE_OK, MCE_EINVAL, MCE_ENOMEM, MCE_ENOSPC, MCE_EDEVICE, MCE_ENOTSUP = 0, -1, -2, -3, -4, -5
+MCE_OK, MCE_EINVAL, MCE_ENOMEM, MCE_ENOSPC, MCE_EDEVICE, MCE_ENOTSUP, MCE_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 RANKS = {"degree": 0, "degeneracy": 1, "triangle": 2, "ttt_root": 3, "peel": 4}
 SCHEDS = {"degree": 0, "triangle": 1, "cost": 2, "id": 3}
 
@@ -49,7 +49,8 @@ class _Result(ctypes.Structure):
                 ("donated", ctypes.c_uint64), ("subproblems", ctypes.c_uint64), ("max_cand", ctypes.c_uint64),
                 ("alg_ops", ctypes.c_uint64), ("rank_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("enum_ms", ctypes.c_double),
                 ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("diag", ctypes.c_uint64 * 8),
-                ("compact_ms", ctypes.c_double), ("handed", ctypes.c_uint64)]
+                ("compact_ms", ctypes.c_double), ("handed", ctypes.c_uint64), ("exec_ops", ctypes.c_uint64),
+                ("lds_bytes", ctypes.c_uint64)]
 
 
 class _CliqueBuf(ctypes.Structure):
@@ -71,6 +72,7 @@ class _ImceResult(ctypes.Structure):
 
 
 EXPORTS = ("mce_static", "mce_static_noalloc", "mce_rank_metric", "mce_features", "imce_create", "imce_add_edges", "imce_remove_edges",
+           "imce_submit", "imce_collect", "imce_device_bytes", "imce_batch_bytes",
            "imce_info",
            "imce_destroy", "mce_strerror", "mce_last_error", "mce_mlp_param_count", "mce_mlp_forward",
            "mce_mlp_forward_bf16", "mce_mlp_grad", "mce_mlp_adam", "mce_mlp_fit_norm", "mce_mlp_to_bf16",
@@ -100,6 +102,12 @@ def lib():
                                      ctypes.c_int, ctypes.POINTER(_ImceResult), ctypes.POINTER(_CliqueBuf),
                                      ctypes.POINTER(_CliqueBuf)]
         L.imce_remove_edges.argtypes = L.imce_add_edges.argtypes
+        L.imce_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.c_int]
+        L.imce_collect.argtypes = [ctypes.c_void_p, ctypes.POINTER(_ImceResult), ctypes.POINTER(_CliqueBuf),
+                                   ctypes.POINTER(_CliqueBuf)]
+        L.imce_device_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+        L.imce_batch_bytes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
         L.imce_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.imce_destroy.argtypes = [ctypes.c_void_p]
@@ -334,6 +342,58 @@ class ImceState:
         """imce_remove_edges (deletions by reduction to additions): same result
         layout as add."""
         return self._update(lib().imce_remove_edges, src, dst, cliques, cap_cliques, cap_verts)
+
+    def device_bytes(self) -> int:
+        """imce_device_bytes: device memory the state holds now."""
+        b = ctypes.c_uint64()
+        _check(lib().imce_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def batch_bytes(self, rho: int) -> int:
+        """imce_batch_bytes: device memory a batch of rho edges may add."""
+        b = ctypes.c_uint64()
+        _check(lib().imce_batch_bytes(self._h, int(rho), ctypes.byref(b)))
+        return b.value
+
+    def submit(self, src, dst, remove: bool = False):
+        """imce_submit: the batch's search now, its subsumed pass on the
+        state's second stream; collect() returns the result."""
+        torch = self._torch
+        s = torch.as_tensor(np.ascontiguousarray(np.asarray(src, dtype=np.uint32)).view(np.int32)).cuda()
+        d = torch.as_tensor(np.ascontiguousarray(np.asarray(dst, dtype=np.uint32)).view(np.int32)).cuda()
+        rho = int(s.numel())
+        _check(lib().imce_submit(self._h, s.data_ptr() if rho else None, d.data_ptr() if rho else None, rho, 1,
+                                 1 if remove else 0))
+
+    def collect(self, cliques: bool = False, cap_cliques: int = 1 << 14, cap_verts: int = 1 << 18):
+        """imce_collect: the oldest submitted batch's result (same layout as add)."""
+        torch = self._torch
+        res = _ImceResult()
+        if not cliques:
+            _check(lib().imce_collect(self._h, ctypes.byref(res), None, None))
+            return {k: getattr(res, k) for k, _ in _ImceResult._fields_}
+        cc, cv = cap_cliques, cap_verts
+        for _ in range(3):
+            bufs, cbs = [], []
+            for _k in range(2):
+                off = torch.zeros(cc + 1, dtype=torch.int64, device="cuda")
+                vert = torch.zeros(max(cv, 1), dtype=torch.int32, device="cuda")
+                bufs.append((off, vert))
+                cbs.append(_CliqueBuf(cc, cv, off.data_ptr(), vert.data_ptr(), 1, 0, 0))
+            rc = lib().imce_collect(self._h, ctypes.byref(res), ctypes.byref(cbs[0]), ctypes.byref(cbs[1]))
+            if rc == MCE_ENOSPC:  # the batch stays to be collected: grow and ask again
+                cc = max(cc, int(cbs[0].n_cliques), int(cbs[1].n_cliques))
+                cv = max(cv, int(cbs[0].n_verts), int(cbs[1].n_verts))
+                continue
+            _check(rc)
+            out = {k: getattr(res, k) for k, _ in _ImceResult._fields_}
+            for name, cb, (off, vert) in zip(("new", "del"), cbs, bufs):
+                nc = int(cb.n_cliques)
+                offn = off[:nc + 1].cpu().numpy().view(np.uint64)
+                vn = vert[:int(cb.n_verts)].cpu().numpy().view(np.uint32)
+                out[name] = sorted(_decode_cliques(offn, vn, nc))
+            return out
+        raise MceError(MCE_ENOSPC, "clique buffer sizing did not converge")
 
     def _update(self, fn, src, dst, cliques, cap_cliques, cap_verts):
         torch = self._torch

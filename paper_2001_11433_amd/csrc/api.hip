@@ -633,6 +633,8 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   out->nodes_total = stats[5] + ctl[CTL_NODES] + (rank == MCE_RANK_TTT_ROOT ? 1 : 0);
   out->donated = ctl[CTL_DONATED];
   out->alg_ops = ctl[CTL_OPS];
+  out->exec_ops = ctl[CTL_OPS_EXEC];
+  out->lds_bytes = ctl[CTL_LDS_BYTES];
   for (int k = 0; k < 8; ++k) out->diag[k] = ctl[CTL_DIAG + k];
   out->compact_ms = job.hand_ms;
   out->handed = job.handed;
@@ -699,6 +701,7 @@ const char* mce_strerror(int code) {
     case MCE_ENOSPC: return "output buffer too small";
     case MCE_EDEVICE: return "HIP runtime error";
     case MCE_ENOTSUP: return "input outside the supported envelope";
+    case MCE_ECANCELED: return "batch dropped after an earlier batch failed";
   }
   return "unknown error";
 }

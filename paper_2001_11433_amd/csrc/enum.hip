@@ -90,7 +90,16 @@ __device__ __forceinline__ void hist_flush(const EnumArgs& a, const uint64_t* lh
 // sums of s and |ext| and multiplies once at the end (ops()).
 struct Acc {
   uint64_t tn, tc, th, ssum, esum;
+  uint64_t cssum, cesum;  // the part of ssum, esum from compact (re-based) nodes
   __device__ uint64_t ops(uint32_t wv) const { return (3 * ssum + 2 * esum) * wv + 2 * ssum; }
+  // the same operations at the width the kernels execute: a wide node's rows
+  // span the subproblem's wp 64-bit cand words, a compact node's one
+  __device__ uint64_t exec_ops(uint32_t wp) const {
+    const uint64_t ws = ssum - cssum, we = esum - cesum;
+    return (3 * ws + 2 * we) * (2ULL * wp) + 2 * ws + (3 * cssum + 2 * cesum) * 2 + 2 * cssum;
+  }
+  // algorithmic LDS bytes of the formula 4 * w * (s + |ext|)
+  __device__ uint64_t lds_bytes(uint32_t wv) const { return 4ULL * wv * (ssum + esum); }
 };
 
 // Per-wave diagnostic counters (see mce_result.diag).
@@ -424,8 +433,11 @@ struct VTally {
     acc.tn += tn;
     acc.tc += tc;
     acc.th += wave_sum_u64(vh);
-    acc.ssum += ss + wave_sum_u64(vss);
+    const uint64_t sc = ss + wave_sum_u64(vss);
+    acc.ssum += sc;
     acc.esum += es;
+    acc.cssum += sc;
+    acc.cesum += es;
   }
 };
 
@@ -821,7 +833,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   const int lane = threadIdx.x;
   uint64_t* const gstk = a.stacks + (uint64_t)blockIdx.x * a.stack_words;
   uint32_t* const gK = a.kbig ? a.kbig + (uint64_t)blockIdx.x * kKBig : nullptr;
-  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
+  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0, tot_xops = 0, tot_lds = 0;
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
   Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -846,7 +858,7 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;  // subproblem universe in 32-bit words
-    Acc acc = {0, 0, 0, 0, 0};
+    Acc acc = {0, 0, 0, 0, 0, 0, 0};
     bool overflow = false;
     // K list: LDS unless this subproblem's cliques (at most |K at the root| +
     // p vertices) could outgrow it; then the wave's global region
@@ -1195,6 +1207,8 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     tot_c += acc.tc;
     tot_h += acc.th;
     tot_ops += acc.ops(wv);
+    tot_xops += acc.exec_ops((p + 63) >> 6);
+    tot_lds += acc.lds_bytes(wv);
   }
   hist_flush(a, L.hist);
   if (lane == 0) {
@@ -1202,6 +1216,8 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
     if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
     if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
+    if (tot_xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)tot_xops);
+    if (tot_lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)tot_lds);
     const uint64_t t_all = now() - t_start;
     // donation inside the compact path is also inside t_compact
     const uint64_t t_wide = t_all - dg.t_idle - dg.t_rebase - dg.t_compact;
@@ -1224,7 +1240,7 @@ template <bool EXCL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_compact(EnumArgs a) {
   __shared__ LdsC L;
   const int lane = threadIdx.x;
-  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0;
+  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0, tot_xops = 0, tot_lds = 0;
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
   Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1239,7 +1255,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     ++dg.tasks;
     const bool pooled = (ref >> 63) != 0;
     const uint64_t idx = ref & 0xFFFFFFFFULL;
-    Acc acc = {0, 0, 0, 0, 0};
+    Acc acc = {0, 0, 0, 0, 0, 0, 0};
     Compact c;
     uint64_t P, Xp = 0, Xx, ext = 0, D = 0, zsum, F;
     uint32_t klen, s;
@@ -1270,6 +1286,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     tot_c += acc.tc;
     tot_h += acc.th;
     tot_ops += acc.ops(wv);
+    tot_xops += acc.exec_ops((p + 63) >> 6);
+    tot_lds += acc.lds_bytes(wv);
   }
   hist_flush(a, L.hist);
   if (lane == 0) {
@@ -1277,6 +1295,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
     if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
     if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
+    if (tot_xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)tot_xops);
+    if (tot_lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)tot_lds);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 1], (unsigned long long)dg.cnodes);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 4], (unsigned long long)dg.t_compact);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 5], (unsigned long long)dg.t_idle);

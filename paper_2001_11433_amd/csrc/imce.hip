@@ -26,6 +26,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "dev.h"
@@ -33,21 +34,49 @@
 
 using namespace mce;
 
+// One batch between its search (phase A) and the collection of its result.
+struct BatchSlot {
+  DevBuf new_off, new_vert;  // cliques of the edge subproblems (the search's output)
+  DevBuf dk, hk;             // the batch's sorted directed keys (u*n + v, both orientations) and edge keys
+  DevBuf del_off, del_vert;  // the subsumed pass's de-duplicated cliques
+  uint64_t cap_nc = 0, cap_nv = 0;
+  bool remove = false;
+  int prev = -1, next = -1;  // CSR buffer before and after the batch
+  uint64_t m = 0, nd = 0, nnz_prev = 0, nnz_next = 0, nc_new = 0, nv_new = 0, dnc = 0, dnv = 0;
+  uint64_t n_srch = 0, h_srch = 0, n_sub = 0, h_sub = 0;
+  imce_result res;
+  int rc = MCE_OK;           // of the subsumed pass
+  char err[256] = "";
+};
+
 struct imce_state {
-  uint64_t n = 0, nnz = 0;
-  DevBuf rp[2], col[2];
+  uint64_t n = 0, nnz = 0;      // the graph the next batch applies to
+  DevBuf rp[3], col[3];         // three CSR buffers: a batch's graph before, after, and the next batch's after
   int cur = 0;
-  uint64_t count = 0, hash = 0;
+  uint64_t count = 0, hash = 0; // clique count and set hash after the last batch whose subsumed pass finished
   mce_opts opts;
+  // phase A (canonicalise, G +/- H, search)
   DevBuf bsrc, bdst, keys, idx, keys2, idx2, keep, pos, eu, ev, hkeys, hidx, hkeys2, hidx2, dkeys, didx, dkeys2, didx2,
-      addcnt, degw, p, x, words, gwords, off, goff, stats, arena, gids, order, bad, new_off, new_vert, cand_off,
-      cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, sdefer, sbig, del_off, del_vert;
-  uint64_t cap_nc = 0, cap_nv = 0, cap_cc = 0, cap_cv = 0;
+      degw, p, x, words, gwords, off, goff, stats, arena, gids, order, bad;
   EnumWork ew;
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
   void* sort_tmp = nullptr;
   size_t sort_bytes = 0;
+  // phase B (subsumed pass), one batch at a time
+  DevBuf cand_off, cand_vert, cand_hash, cand_id, chash2, chash3, cid2, uniq, sctl, sdefer, sbig;
+  uint64_t cap_cc = 0, cap_cv = 0;
+  uint64_t arena_per_edge = 0;  // largest edge-subproblem arena bytes per applied edge seen
+  void* sort_tmp_b = nullptr;
+  size_t sort_bytes_b = 0;
+  // pipelined use (imce_submit / imce_collect): two slots, a FIFO of the
+  // batches not yet collected, and the helper thread running a subsumed pass
+  BatchSlot slot[2];
+  int fifo[2] = {-1, -1};
+  int nfifo = 0;
+  hipStream_t sub_stream = nullptr;
+  std::thread sub_thread;
+  int sub_slot = -1;            // slot whose subsumed pass runs on sub_thread
 };
 
 namespace {
@@ -741,20 +770,14 @@ __global__ void k_dedup(uint64_t nc, const uint64_t* __restrict__ shash, const u
 
 __global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
 
-int sort_pairs_u64_u32(imce_state* st, uint64_t* k, uint32_t* v, uint64_t* k2, uint32_t* v2, uint64_t nitems,
-                       hipStream_t s, uint64_t** ko, uint32_t** vo) {
+int sort_pairs_u64_u32(void*& tmp, size_t& tmp_bytes, uint64_t* k, uint32_t* v, uint64_t* k2, uint32_t* v2,
+                       uint64_t nitems, hipStream_t s, uint64_t** ko, uint32_t** vo) {
   hipcub::DoubleBuffer<uint64_t> kb(k, k2);
   hipcub::DoubleBuffer<uint32_t> vb(v, v2);
   size_t need = 0;
   MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)nitems, 0, 64, s));
-  if (need > st->sort_bytes) {
-    if (st->sort_tmp) MCE_TRY_HIP(hipFree(st->sort_tmp));
-    st->sort_tmp = nullptr;
-    st->sort_bytes = 0;
-    MCE_TRY_HIP(hipMalloc(&st->sort_tmp, need));
-    st->sort_bytes = need;
-  }
-  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(st->sort_tmp, need, kb, vb, (int)nitems, 0, 64, s));
+  MCE_TRY(ensure_temp(tmp, tmp_bytes, need));
+  MCE_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)nitems, 0, 64, s));
   *ko = kb.Current();
   *vo = vb.Current();
   return MCE_OK;
@@ -780,39 +803,66 @@ int copy_cliques_out(mce_clique_buf* out, const uint64_t* off, const uint32_t* v
   return MCE_OK;
 }
 
-// One batch of edge additions (remove = false) or deletions (remove = true).
+// Device time between two events (0 when either is missing).
+double event_ms(hipEvent_t a, hipEvent_t b) {
+  float t = 0;
+  if (!a || !b || hipEventElapsedTime(&t, a, b) != hipSuccess) return 0;
+  return t;
+}
+
+struct Events {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  int init() {
+    for (auto& x : e) MCE_TRY_HIP(hipEventCreate(&x));
+    return MCE_OK;
+  }
+};
+
+// A CSR buffer for a batch's graph after the batch: neither the current one
+// nor `keep` (the graph a pending subsumed pass still reads).
+int free_buffer(const imce_state* st, int keep) {
+  for (int b = 0; b < 3; ++b)
+    if (b != st->cur && b != keep) return b;
+  return -1;
+}
+
+// Phase A of one batch of edge additions (remove = false) or deletions
+// (remove = true) into slot `si`: canonicalise, build the graph after the
+// batch into a free CSR buffer (`keep` is protected), run the edge
+// subproblems (new cliques).  On success the state's current graph is the
+// one after the batch; on error the state is as it was.
+//
 // A deletion is the reduction of Section 5.3: with G' = G - H, G = G' + H, so
 // the edge-subproblem search over G finds Lambda_new(G', H) = the cliques that
 // stop being maximal, and the subsumed pass over G' finds Lambda_del(G', H) =
 // the cliques that become maximal.  The same kernels run with the roles of
-// the two CSR buffers swapped: the search always runs on the graph that holds
-// H, the maximality test on the graph without it.
-int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
-                imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl, bool remove) {
-  // the search's cliques and the subsumed pass's cliques, as the caller names them
-  mce_clique_buf* search_cl = remove ? del_cl : new_cl;
-  mce_clique_buf* sub_cl = remove ? new_cl : del_cl;
+// the two graphs swapped: the search always runs on the graph that holds H,
+// the maximality test on the graph without it.
+int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device, bool remove,
+            int si, int keep) {
+  BatchSlot& b = st->slot[si];
   hipStream_t s = (hipStream_t)st->opts.hip_stream;
-  std::memset(res, 0, sizeof(*res));
   const uint64_t n = st->n;
-  res->count = st->count;
-  res->set_hash = st->hash;
-  if (new_cl) new_cl->n_cliques = new_cl->n_verts = 0;
-  if (del_cl) del_cl->n_cliques = del_cl->n_verts = 0;
+  std::memset(&b.res, 0, sizeof(b.res));
+  b.remove = remove;
+  b.rc = MCE_OK;
+  b.err[0] = 0;
+  b.m = b.nd = b.nc_new = b.nv_new = b.dnc = b.dnv = 0;
+  b.n_srch = b.h_srch = b.n_sub = b.h_sub = 0;
+  b.prev = b.next = st->cur;
+  b.nnz_prev = b.nnz_next = st->nnz;
   if (rho == 0) return MCE_OK;
   if (!src || !dst) {
     set_error("NULL batch arrays");
     return MCE_EINVAL;
   }
-  hipEvent_t ev[4];
-  for (auto& e : ev) MCE_TRY_HIP(hipEventCreate(&e));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
-    }
-  } guard{ev};
-  MCE_TRY_HIP(hipEventRecord(ev[0], s));
+  Events evs;
+  MCE_TRY(evs.init());
+  MCE_TRY_HIP(hipEventRecord(evs.e[0], s));
 
   const uint64_t* rp = st->rp[st->cur].as<uint64_t>();
   const uint32_t* col = st->col[st->cur].as<uint32_t>();
@@ -835,7 +885,7 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   MCE_TRY(st->keep.ensure(rho * 8));
   MCE_TRY(st->pos.ensure(rho * 8));
   MCE_TRY(st->bad.ensure(8));
-  MCE_TRY_HIP(hipMemsetAsync(st->bad.p, 0, 4, s));
+  MCE_TRY_HIP(dev_zero(st->bad.p, 4, s));
   hipLaunchKernelGGL(k_canon, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, dsrc, ddst, n, st->keys.as<uint64_t>(),
                      st->idx.as<uint32_t>(), st->bad.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
@@ -848,8 +898,8 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   }
   uint64_t* skeys;
   uint32_t* sidx;
-  MCE_TRY(sort_pairs_u64_u32(st, st->keys.as<uint64_t>(), st->idx.as<uint32_t>(), st->keys2.as<uint64_t>(),
-                             st->idx2.as<uint32_t>(), rho, s, &skeys, &sidx));
+  MCE_TRY(sort_pairs_u64_u32(st->sort_tmp, st->sort_bytes, st->keys.as<uint64_t>(), st->idx.as<uint32_t>(),
+                             st->keys2.as<uint64_t>(), st->idx2.as<uint32_t>(), rho, s, &skeys, &sidx));
   hipLaunchKernelGGL(k_keep, dim3(blocks_for(rho, 256)), dim3(256), 0, s, rho, skeys, sidx, n, rp, col,
                      remove ? 1 : 0, st->keep.as<uint64_t>());
   MCE_TRY_HIP(hipGetLastError());
@@ -859,14 +909,12 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   MCE_TRY_HIP(hipMemcpyAsync(&lastkeep, st->keep.as<uint64_t>() + rho - 1, 8, hipMemcpyDeviceToHost, s));
   MCE_TRY_HIP(hipStreamSynchronize(s));
   const uint64_t m = lastpos + lastkeep;  // applied edges
-  res->n_applied = m;
-  res->n_skipped = rho - m;
+  b.res.n_applied = m;
+  b.res.n_skipped = rho - m;
   if (m == 0) {
-    MCE_TRY_HIP(hipEventRecord(ev[3], s));
+    MCE_TRY_HIP(hipEventRecord(evs.e[1], s));
     MCE_TRY_HIP(hipStreamSynchronize(s));
-    float t = 0;
-    (void)hipEventElapsedTime(&t, ev[0], ev[3]);
-    res->ms = t;
+    b.res.new_ms = event_ms(evs.e[0], evs.e[1]);
     return MCE_OK;
   }
   const uint64_t nd = 2 * m;
@@ -886,15 +934,21 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   MCE_TRY_HIP(hipGetLastError());
   uint64_t* hk;
   uint32_t* hi;
-  MCE_TRY(sort_pairs_u64_u32(st, st->hkeys.as<uint64_t>(), st->hidx.as<uint32_t>(), st->hkeys2.as<uint64_t>(),
-                             st->hidx2.as<uint32_t>(), m, s, &hk, &hi));
+  MCE_TRY(sort_pairs_u64_u32(st->sort_tmp, st->sort_bytes, st->hkeys.as<uint64_t>(), st->hidx.as<uint32_t>(),
+                             st->hkeys2.as<uint64_t>(), st->hidx2.as<uint32_t>(), m, s, &hk, &hi));
   uint64_t* dk;
   uint32_t* di;
-  MCE_TRY(sort_pairs_u64_u32(st, st->dkeys.as<uint64_t>(), st->didx.as<uint32_t>(), st->dkeys2.as<uint64_t>(),
-                             st->didx2.as<uint32_t>(), nd, s, &dk, &di));
+  MCE_TRY(sort_pairs_u64_u32(st->sort_tmp, st->sort_bytes, st->dkeys.as<uint64_t>(), st->didx.as<uint32_t>(),
+                             st->dkeys2.as<uint64_t>(), st->didx2.as<uint32_t>(), nd, s, &dk, &di));
+  // the subsumed pass reads the sorted keys after the next batch has reused
+  // these buffers: keep a copy in the slot
+  MCE_TRY(b.dk.ensure(nd * 8));
+  MCE_TRY(b.hk.ensure(m * 8));
+  MCE_TRY_HIP(hipMemcpyAsync(b.dk.p, dk, nd * 8, hipMemcpyDeviceToDevice, s));
+  MCE_TRY_HIP(hipMemcpyAsync(b.hk.p, hk, m * 8, hipMemcpyDeviceToDevice, s));
 
-  // 2. G' = G + H
-  const int nxt = st->cur ^ 1;
+  // 2. the graph after the batch, G + H or G - H, into a free buffer
+  const int nxt = free_buffer(st, keep);
   const uint64_t nnz2 = remove ? st->nnz - nd : st->nnz + nd;
   MCE_TRY(st->degw.ensure(n * 8));
   MCE_TRY(st->rp[nxt].ensure((n + 1) * 8));
@@ -913,11 +967,9 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   else
     hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
   MCE_TRY_HIP(hipGetLastError());
-  // the graph that holds H (searched) and the one without it (maximality test)
+  // the search runs on the graph that holds H
   const uint64_t* srp = remove ? rp : rpn;
   const uint32_t* scol = remove ? col : coln;
-  const uint64_t* mrp = remove ? rpn : rp;
-  const uint32_t* mcol = remove ? coln : col;
 
   // 3. new cliques: one edge subproblem per applied edge
   MCE_TRY(st->p.ensure(m * 4));
@@ -928,7 +980,7 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   MCE_TRY(st->goff.ensure(m * 8));
   MCE_TRY(st->order.ensure(m * 4));
   MCE_TRY(st->stats.ensure(8 * 8));
-  MCE_TRY_HIP(hipMemsetAsync(st->stats.p, 0, 64, s));
+  MCE_TRY_HIP(dev_zero(st->stats.p, 64, s));
   hipLaunchKernelGGL(k_edge_sizes, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
                      st->ev.as<uint32_t>(), srp, scol, st->p.as<uint32_t>(), st->x.as<uint32_t>(),
                      st->words.as<uint64_t>(), st->gwords.as<uint64_t>(), st->stats.as<uint64_t>());
@@ -948,9 +1000,10 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
     return MCE_ENOTSUP;
   }
   const uint64_t aw = std::max<uint64_t>(tl[0] + tl[1], 1), gw = std::max<uint64_t>(tl[2] + tl[3], 1);
+  st->arena_per_edge = std::max<uint64_t>(st->arena_per_edge, (aw * 8 + m - 1) / m);
   MCE_TRY(st->arena.ensure(aw * 8));
   MCE_TRY(st->gids.ensure(gw * 4));
-  MCE_TRY_HIP(hipMemsetAsync(st->arena.p, 0, aw * 8, s));
+  MCE_TRY_HIP(dev_zero(st->arena.p, aw * 8, s));
   hipLaunchKernelGGL(k_edge_gids, dim3(blocks_for(m * 64, 256)), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
                      st->ev.as<uint32_t>(), srp, scol, st->goff.as<uint64_t>(), st->gids.as<uint32_t>());
   const uint32_t row_chunks = (uint32_t)std::max<uint64_t>((stats[0] + kEdgeRowsPerWave - 1) / kEdgeRowsPerWave, 1);
@@ -960,14 +1013,14 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   hipLaunchKernelGGL(k_iota32, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, st->order.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
 
-  if (st->cap_nc == 0) {
-    st->cap_nc = 1 << 20;
-    st->cap_nv = 1 << 24;
+  if (b.cap_nc == 0) {
+    b.cap_nc = 1 << 20;
+    b.cap_nv = 1 << 24;
   }
   uint64_t ctl[CTL_WORDS];
   for (int attempt = 0;; ++attempt) {
-    MCE_TRY(st->new_off.ensure((st->cap_nc + 1) * 8));
-    MCE_TRY(st->new_vert.ensure(st->cap_nv * 4));
+    MCE_TRY(b.new_off.ensure((b.cap_nc + 1) * 8));
+    MCE_TRY(b.new_vert.ensure(b.cap_nv * 4));
     EnumJob job;
     job.sub.off = st->off.as<uint64_t>();
     job.sub.goff = st->goff.as<uint64_t>();
@@ -983,35 +1036,65 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
     job.max_frame = stats[1];
     job.excl = true;
     job.nodes_v = job.count_v = job.hash_v = nullptr;
-    job.cl_off = st->new_off.as<uint64_t>();
-    job.cl_vert = st->new_vert.as<uint32_t>();
-    job.cap_cliques = st->cap_nc;
-    job.cap_verts = st->cap_nv;
+    job.cl_off = b.new_off.as<uint64_t>();
+    job.cl_vert = b.new_vert.as<uint32_t>();
+    job.cap_cliques = b.cap_nc;
+    job.cap_verts = b.cap_nv;
     job.opts = &st->opts;
     job.hand_initial_units = kStateHandUnits;
     MCE_TRY(run_enum(job, st->ew, s, ctl, nullptr));
-    res->nodes = ctl[CTL_NODES];
-    res->handed = job.handed;
-    res->compact_ms = job.hand_ms;
+    b.res.nodes = ctl[CTL_NODES];
+    b.res.handed = job.handed;
+    b.res.compact_ms = job.hand_ms;
     if (ctl[CTL_FLAGS] & 2ULL) {
       set_error("new cliques exceed 2^32 vertices or a clique exceeds the supported size");
       return MCE_ENOTSUP;
     }
     const uint64_t nc = ctl[CTL_CLQ] >> 32, nv = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
-    if (nc <= st->cap_nc && nv <= st->cap_nv) break;
+    if (nc <= b.cap_nc && nv <= b.cap_nv) break;
     if (attempt >= 2) {
       set_error("new-clique buffer sizing did not converge");
       return MCE_ENOMEM;
     }
-    st->cap_nc = std::max(st->cap_nc, nc);
-    st->cap_nv = std::max(st->cap_nv, nv);
+    b.cap_nc = std::max(b.cap_nc, nc);
+    b.cap_nv = std::max(b.cap_nv, nv);
   }
-  const uint64_t n_srch = ctl[CTL_COUNT], h_srch = ctl[CTL_HASH];
-  const uint64_t nc_new = ctl[CTL_CLQ] >> 32, nv_new = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
-  MCE_TRY_HIP(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, st->new_off.as<uint64_t>() + nc_new, nv_new);
+  b.n_srch = ctl[CTL_COUNT];
+  b.h_srch = ctl[CTL_HASH];
+  b.nc_new = ctl[CTL_CLQ] >> 32;
+  b.nv_new = ctl[CTL_CLQ] & 0xFFFFFFFFULL;
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, b.new_off.as<uint64_t>() + b.nc_new, b.nv_new);
+  MCE_TRY_HIP(hipGetLastError());
+  MCE_TRY_HIP(hipEventRecord(evs.e[1], s));
+  MCE_TRY_HIP(hipStreamSynchronize(s));
+  b.res.new_ms = event_ms(evs.e[0], evs.e[1]);
+  b.m = m;
+  b.nd = nd;
+  b.prev = st->cur;
+  b.next = nxt;
+  b.nnz_next = nnz2;
+  // the graph the next batch applies to
+  st->cur = nxt;
+  st->nnz = nnz2;
+  return MCE_OK;
+}
 
-  // 4. subsumed cliques
+// Phase B of slot `si` on stream `s`: the subsumed pass (Algorithm 7) over the
+// search's cliques, tested for maximality in the graph without H, then exact
+// de-duplication (always written to the slot's lists).  Sets b.n_sub, b.h_sub,
+// b.dnc, b.dnv.  Touches only the phase-B buffers and the slot.
+int phase_b(imce_state* st, int si, hipStream_t s) {
+  BatchSlot& b = st->slot[si];
+  if (b.m == 0) return MCE_OK;
+  const uint64_t n = st->n, m = b.m, nd = b.nd, nc_new = b.nc_new;
+  const int mb = b.remove ? b.next : b.prev;  // the graph without H
+  const uint64_t* mrp = st->rp[mb].as<uint64_t>();
+  const uint32_t* mcol = st->col[mb].as<uint32_t>();
+  const uint64_t* hk = b.hk.as<uint64_t>();
+  const uint64_t* dk = b.dk.as<uint64_t>();
+  Events evs;
+  MCE_TRY(evs.init());
+  MCE_TRY_HIP(hipEventRecord(evs.e[0], s));
   if (st->cap_cc == 0) {
     st->cap_cc = 1 << 20;
     st->cap_cv = 1 << 24;
@@ -1024,7 +1107,7 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
     MCE_TRY(st->sctl.ensure(4 * 8));
     MCE_TRY(st->sdefer.ensure(std::max<uint64_t>(nc_new, 1) * 4));
     MCE_TRY(st->sbig.ensure(std::max<uint64_t>(nc_new, 1) * 4));
-    MCE_TRY_HIP(hipMemsetAsync(st->sctl.p, 0, 32, s));
+    MCE_TRY_HIP(dev_zero(st->sctl.p, 32, s));
     if (nc_new) {
       // most new cliques hold one or two batch edges: a small-LDS pass with
       // many waves per CU, then the rest with room for kSubMaxS subsets
@@ -1033,18 +1116,18 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
       uint32_t* defer = st->sdefer.as<uint32_t>();
       uint32_t* big = st->sbig.as<uint32_t>();
       hipLaunchKernelGGL((k_subsumed<kSubFastS, kSubFastPairs>), dim3(grid), dim3(64), 0, s, nc_new, nullptr, nullptr,
-                         defer, big, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, mrp, mcol, hk, m, dk,
+                         defer, big, b.new_off.as<uint64_t>(), b.new_vert.as<uint32_t>(), n, mrp, mcol, hk, m, dk,
                          nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       hipLaunchKernelGGL((k_subsumed<kSubMaxS, kSubMaxPairs>), dim3(1024), dim3(64), 0, s, nc_new, defer, sc + 2,
-                         nullptr, nullptr, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), n, mrp, mcol, hk, m,
+                         nullptr, nullptr, b.new_off.as<uint64_t>(), b.new_vert.as<uint32_t>(), n, mrp, mcol, hk, m,
                          dk, nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       // new cliques above kSubMaxK vertices (rare: a batch edge inside a very large clique)
-      hipLaunchKernelGGL(k_subsumed_big, dim3(256), dim3(64), 0, s, big, sc + 3, st->new_off.as<uint64_t>(),
-                         st->new_vert.as<uint32_t>(), n, mrp, mcol, dk, nd, sc, st->cand_off.as<uint64_t>(),
+      hipLaunchKernelGGL(k_subsumed_big, dim3(256), dim3(64), 0, s, big, sc + 3, b.new_off.as<uint64_t>(),
+                         b.new_vert.as<uint32_t>(), n, mrp, mcol, dk, nd, sc, st->cand_off.as<uint64_t>(),
                          st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
     }
@@ -1067,14 +1150,9 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
   const uint64_t ncand = sctl[0] >> 32, nvcand = sctl[0] & 0xFFFFFFFFULL;
   uint64_t uctl[3] = {0, 0, 0};
   MCE_TRY(st->uniq.ensure(4 * 8));
-  MCE_TRY_HIP(hipMemsetAsync(st->uniq.p, 0, 32, s));
-  uint64_t del_cap_c = 0, del_cap_v = 0;
-  if (sub_cl) {
-    del_cap_c = nvcand ? ncand : 0;
-    del_cap_v = nvcand;
-    MCE_TRY(st->del_off.ensure((ncand + 1) * 8));
-    MCE_TRY(st->del_vert.ensure(std::max<uint64_t>(nvcand, 1) * 4));
-  }
+  MCE_TRY_HIP(dev_zero(st->uniq.p, 32, s));
+  MCE_TRY(b.del_off.ensure((ncand + 1) * 8));
+  MCE_TRY(b.del_vert.ensure(std::max<uint64_t>(nvcand, 1) * 4));
   if (ncand) {
     MCE_TRY(st->cand_id.ensure(ncand * 4));
     MCE_TRY(st->chash2.ensure(ncand * 8));
@@ -1085,75 +1163,248 @@ int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64
     uint64_t* sh;
     uint32_t* sid;
     MCE_TRY(st->chash3.ensure(ncand * 8));
-    MCE_TRY(sort_pairs_u64_u32(st, st->chash2.as<uint64_t>(), st->cand_id.as<uint32_t>(), st->chash3.as<uint64_t>(),
-                               st->cid2.as<uint32_t>(), ncand, s, &sh, &sid));
+    MCE_TRY(sort_pairs_u64_u32(st->sort_tmp_b, st->sort_bytes_b, st->chash2.as<uint64_t>(),
+                               st->cand_id.as<uint32_t>(), st->chash3.as<uint64_t>(), st->cid2.as<uint32_t>(), ncand,
+                               s, &sh, &sid));
     hipLaunchKernelGGL(k_dedup, dim3(blocks_for(ncand, 256)), dim3(256), 0, s, ncand, sh, sid,
-                       st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), nvcand,
-                       st->uniq.as<uint64_t>(), sub_cl ? st->del_off.as<uint64_t>() : nullptr,
-                       sub_cl ? st->del_vert.as<uint32_t>() : nullptr, del_cap_c, del_cap_v);
+                       st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(), nvcand, st->uniq.as<uint64_t>(),
+                       b.del_off.as<uint64_t>(), b.del_vert.as<uint32_t>(), nvcand ? ncand : 0, nvcand);
     MCE_TRY_HIP(hipGetLastError());
     MCE_TRY_HIP(hipMemcpyAsync(uctl, st->uniq.p, 24, hipMemcpyDeviceToHost, s));
   }
-  MCE_TRY_HIP(hipEventRecord(ev[2], s));
+  MCE_TRY_HIP(hipEventRecord(evs.e[1], s));
   MCE_TRY_HIP(hipStreamSynchronize(s));
-  const uint64_t n_sub = uctl[0], h_sub = uctl[1];
+  b.n_sub = uctl[0];
+  b.h_sub = uctl[1];
+  b.dnc = uctl[2] >> 32;
+  b.dnv = uctl[2] & 0xFFFFFFFFULL;
+  b.res.sub_ms = event_ms(evs.e[0], evs.e[1]);
+  return MCE_OK;
+}
 
-  // caller buffers: report sizes; too small -> no commit
+// The result fields of a slot after both phases (new / del as the caller
+// names them, count and hash after the batch given the count and hash before).
+void finish_result(const BatchSlot& b, uint64_t count_before, uint64_t hash_before, imce_result* r) {
+  *r = b.res;
+  r->n_new = b.remove ? b.n_sub : b.n_srch;
+  r->n_del = b.remove ? b.n_srch : b.n_sub;
+  r->hash_new = b.remove ? b.h_sub : b.h_srch;
+  r->hash_del = b.remove ? b.h_srch : b.h_sub;
+  r->count = count_before + r->n_new - r->n_del;
+  r->set_hash = hash_before + r->hash_new - r->hash_del;
+  r->ms = b.res.new_ms + b.res.sub_ms;
+}
+
+// Copies a slot's clique lists to the caller's buffers (sizes always written).
+int copy_slot_out(const BatchSlot& b, mce_clique_buf* new_cl, mce_clique_buf* del_cl, hipStream_t s) {
+  mce_clique_buf* search_cl = b.remove ? del_cl : new_cl;
+  mce_clique_buf* sub_cl = b.remove ? new_cl : del_cl;
+  if (new_cl) new_cl->n_cliques = new_cl->n_verts = 0;
+  if (del_cl) del_cl->n_cliques = del_cl->n_verts = 0;
+  if (b.m == 0) return MCE_OK;
   int rc = MCE_OK;
   if (search_cl) {
-    int r = copy_cliques_out(search_cl, st->new_off.as<uint64_t>(), st->new_vert.as<uint32_t>(), nc_new, nv_new, s);
+    int r = copy_cliques_out(search_cl, b.new_off.as<uint64_t>(), b.new_vert.as<uint32_t>(), b.nc_new, b.nv_new, s);
     if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
     else if (r != MCE_OK) return r;
   }
   if (sub_cl) {
-    const uint64_t dnc = uctl[2] >> 32, dnv = uctl[2] & 0xFFFFFFFFULL;
-    int r = copy_cliques_out(sub_cl, st->del_off.as<uint64_t>(), st->del_vert.as<uint32_t>(), dnc, dnv, s);
+    int r = copy_cliques_out(sub_cl, b.del_off.as<uint64_t>(), b.del_vert.as<uint32_t>(), b.dnc, b.dnv, s);
     if (r == MCE_ENOSPC) rc = MCE_ENOSPC;
     else if (r != MCE_OK) return r;
   }
   MCE_TRY_HIP(hipStreamSynchronize(s));
-  if (rc != MCE_OK) {
-    set_error("clique buffer too small (sizes written back); the batch was not applied");
-    return rc;
-  }
+  return rc;
+}
 
-  // 5. commit
-  st->cur = nxt;
-  st->nnz = nnz2;
-  res->n_new = remove ? n_sub : n_srch;
-  res->n_del = remove ? n_srch : n_sub;
-  res->hash_new = remove ? h_sub : h_srch;
-  res->hash_del = remove ? h_srch : h_sub;
-  st->count = st->count + res->n_new - res->n_del;
-  st->hash = st->hash + res->hash_new - res->hash_del;
-  res->count = st->count;
-  res->set_hash = st->hash;
-  MCE_TRY_HIP(hipEventRecord(ev[3], s));
-  MCE_TRY_HIP(hipStreamSynchronize(s));
-  float t01 = 0, t12 = 0, t03 = 0;
-  (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
-  (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
-  (void)hipEventElapsedTime(&t03, ev[0], ev[3]);
-  res->new_ms = t01;
-  res->sub_ms = t12;
-  res->ms = t03;
+// Waits for the running subsumed pass.  When it failed, the graph returns to
+// the one before that batch, and any later batch (already searched) is
+// discarded; returns that batch's error (MCE_OK otherwise).
+int join_sub(imce_state* st) {
+  if (st->sub_slot < 0) return MCE_OK;
+  st->sub_thread.join();
+  const int si = st->sub_slot;
+  st->sub_slot = -1;
+  BatchSlot& b = st->slot[si];
+  if (b.rc != MCE_OK) {
+    st->cur = b.prev;
+    st->nnz = b.nnz_prev;
+    return b.rc;
+  }
+  // commit the batch's count and hash (passes run in batch order)
+  imce_result r;
+  finish_result(b, st->count, st->hash, &r);
+  st->count = r.count;
+  st->hash = r.set_hash;
+  b.res = r;
   return MCE_OK;
 }
 
+// One batch start to end (imce_add_edges / imce_remove_edges).
+int update_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device,
+                imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl, bool remove) {
+  std::memset(res, 0, sizeof(*res));
+  res->count = st->count;
+  res->set_hash = st->hash;
+  if (new_cl) new_cl->n_cliques = new_cl->n_verts = 0;
+  if (del_cl) del_cl->n_cliques = del_cl->n_verts = 0;
+  if (st->nfifo > 0) {
+    set_error("submitted batches are pending: collect them with imce_collect first");
+    return MCE_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)st->opts.hip_stream;
+  const int prev = st->cur;
+  const uint64_t nnz0 = st->nnz;
+  int rc = phase_a(st, src, dst, rho, on_device, remove, 0, -1);
+  if (rc == MCE_OK) rc = phase_b(st, 0, s);
+  if (rc == MCE_OK) {
+    rc = copy_slot_out(st->slot[0], new_cl, del_cl, s);
+    if (rc == MCE_ENOSPC) set_error("clique buffer too small (sizes written back); the batch was not applied");
+  }
+  if (rc != MCE_OK) {
+    st->cur = prev;  // all or nothing
+    st->nnz = nnz0;
+    return rc;
+  }
+  finish_result(st->slot[0], st->count, st->hash, res);
+  st->count = res->count;
+  st->hash = res->set_hash;
+  return MCE_OK;
+}
+
+// imce_submit: phase A now (overlapping the previous batch's subsumed pass),
+// then the subsumed pass on the state's second stream and a helper thread.
+int submit_impl(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device, bool remove) {
+  if (st->nfifo >= 2) {
+    set_error("two submitted batches are not collected yet: call imce_collect first");
+    return MCE_EINVAL;
+  }
+  const int si = st->nfifo == 0 ? 0 : (st->fifo[0] ^ 1);
+  const int keep = st->sub_slot >= 0 ? st->slot[st->sub_slot].prev : -1;  // read by the running pass
+  int rc = phase_a(st, src, dst, rho, on_device, remove, si, keep);
+  if (rc != MCE_OK) return rc;  // the state (and the pending batch) as before
+  const int rb = join_sub(st);
+  if (rb != MCE_OK) {
+    // the earlier batch failed: the graph went back to before it, and this
+    // batch, searched on top of it, is dropped
+    set_error("an earlier submitted batch failed (collect it for its error); this batch was discarded and the "
+              "state is as before that batch");
+    return MCE_ECANCELED;
+  }
+  BatchSlot* b = &st->slot[si];
+  st->fifo[st->nfifo++] = si;
+  st->sub_slot = si;
+  st->sub_thread = std::thread([st, b, si]() {
+    b->rc = phase_b(st, si, st->sub_stream);
+    if (b->rc != MCE_OK) snprintf(b->err, sizeof(b->err), "%s", mce_last_error());
+  });
+  return MCE_OK;
+}
+
+int collect_impl(imce_state* st, imce_result* res, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+  std::memset(res, 0, sizeof(*res));
+  if (st->nfifo == 0) {
+    set_error("no submitted batch to collect");
+    return MCE_EINVAL;
+  }
+  const int si = st->fifo[0];
+  BatchSlot& b = st->slot[si];
+  if (st->sub_slot == si) join_sub(st);
+  if (b.rc != MCE_OK) {
+    set_error("%s", b.err);
+    const int rc = b.rc;
+    st->fifo[0] = st->fifo[1];
+    --st->nfifo;
+    return rc;
+  }
+  const int rc = copy_slot_out(b, new_cl, del_cl, (hipStream_t)st->opts.hip_stream);
+  *res = b.res;
+  if (rc == MCE_ENOSPC) {
+    set_error("clique buffer too small (sizes written back); the batch stays to be collected");
+    return rc;
+  }
+  if (rc != MCE_OK) return rc;
+  st->fifo[0] = st->fifo[1];
+  --st->nfifo;
+  return MCE_OK;
+}
+
+uint64_t state_bytes(const imce_state* st) {
+  uint64_t t = st->scan_bytes + st->sort_bytes + st->sort_bytes_b + st->ew.sort_bytes;
+  for (const DevBuf* b :
+       {&st->rp[0], &st->rp[1], &st->rp[2], &st->col[0], &st->col[1], &st->col[2], &st->bsrc, &st->bdst, &st->keys,
+        &st->idx, &st->keys2, &st->idx2, &st->keep, &st->pos, &st->eu, &st->ev, &st->hkeys, &st->hidx, &st->hkeys2,
+        &st->hidx2, &st->dkeys, &st->didx, &st->dkeys2, &st->didx2, &st->degw, &st->p, &st->x, &st->words,
+        &st->gwords, &st->off, &st->goff, &st->stats, &st->arena, &st->gids, &st->order, &st->bad, &st->cand_off,
+        &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq, &st->sctl,
+        &st->sdefer, &st->sbig})
+    t += b->bytes;
+  for (const BatchSlot& b : st->slot)
+    for (const DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.del_off, &b.del_vert}) t += d->bytes;
+  for (const DevBuf* d : {&st->ew.queue, &st->ew.ctl, &st->ew.pool, &st->ew.pool_next, &st->ew.stacks, &st->ew.hand,
+                          &st->ew.hand_idx, &st->ew.hkeys, &st->ew.hkeys2, &st->ew.hvals, &st->ew.hvals2,
+                          &st->ew.kbig})
+    t += d->bytes;
+  return t;
+}
+
+// Device memory a batch of rho edges may add to the state, from the sizing
+// rules of phase A and B: every buffer a batch grows to its size for rho
+// applied edges (minus what it already holds), the search tables on the
+// state's first batch, and the edge-subproblem rows at the largest bytes per
+// applied edge seen so far (4 KiB before any batch).
+uint64_t batch_bytes(const imce_state* st, uint64_t rho) {
+  auto grow = [](const DevBuf& b, uint64_t need) -> uint64_t { return need > b.bytes ? need - b.bytes : 0; };
+  const uint64_t n = st->n, m = rho, nd = 2 * rho;
+  uint64_t t = 0;
+  t += grow(st->keys, rho * 8) + grow(st->keys2, rho * 8) + grow(st->idx, rho * 4) + grow(st->idx2, rho * 4) +
+       grow(st->keep, rho * 8) + grow(st->pos, rho * 8) + grow(st->bsrc, rho * 4) + grow(st->bdst, rho * 4);
+  t += grow(st->eu, m * 4) + grow(st->ev, m * 4) + grow(st->hkeys, m * 8) + grow(st->hidx, m * 4) +
+       grow(st->hkeys2, m * 8) + grow(st->hidx2, m * 4) + grow(st->dkeys, nd * 8) + grow(st->didx, nd * 4) +
+       grow(st->dkeys2, nd * 8) + grow(st->didx2, nd * 4);
+  t += grow(st->p, m * 4) + grow(st->x, m * 4) + grow(st->words, m * 8) + grow(st->gwords, m * 8) +
+       grow(st->off, m * 8) + grow(st->goff, m * 8) + grow(st->order, m * 4) + grow(st->degw, n * 8);
+  // the graph after the batch: one more CSR buffer of the current size plus the batch
+  const uint64_t need_csr = (n + 1) * 8 + (st->nnz + nd) * 4;
+  uint64_t spare = 0;
+  for (int b = 0; b < 3; ++b)
+    if (b != st->cur) spare = std::max<uint64_t>(spare, st->rp[b].bytes + st->col[b].bytes);
+  t += need_csr > spare ? need_csr - spare : 0;
+  // edge-subproblem rows and vertex ids
+  const uint64_t per_edge = st->arena_per_edge ? st->arena_per_edge : 4096;
+  t += grow(st->arena, m * per_edge) + grow(st->gids, m * 256);
+  // slot buffers of one batch (the first batch sizes them)
+  const BatchSlot& b = st->slot[0];
+  t += grow(b.dk, nd * 8) + grow(b.hk, m * 8);
+  if (b.cap_nc == 0) t += (1ULL << 20) * 8 + (1ULL << 24) * 4;  // new-clique lists
+  if (st->cap_cc == 0) t += (1ULL << 20) * 16 + (1ULL << 24) * 4 + (1ULL << 20) * 24;  // candidates and dedup
+  // the search's tables (queue, donation pool, handoff arena) on the first batch
+  if (st->ew.pool.bytes == 0)
+    t += (1ULL << 16) * kBlockWords * 8 + (1ULL << 16) * 4 + (m + std::max<uint64_t>(1u << 24, 4 * m)) * 8 +
+         kStateHandUnits * 64 + kStateHandUnits * 4;
+  return t;
+}
+
 void release_state(imce_state* st) {
-  DevBuf* bufs[] = {&st->rp[0], &st->rp[1], &st->col[0], &st->col[1], &st->bsrc, &st->bdst, &st->keys, &st->idx,
-                    &st->keys2, &st->idx2, &st->keep, &st->pos, &st->eu, &st->ev, &st->hkeys, &st->hidx,
-                    &st->hkeys2, &st->hidx2, &st->dkeys, &st->didx, &st->dkeys2, &st->didx2, &st->addcnt,
-                    &st->degw, &st->p, &st->x, &st->words, &st->gwords, &st->off, &st->goff, &st->stats,
-                    &st->arena, &st->gids, &st->order, &st->bad, &st->new_off, &st->new_vert, &st->cand_off,
-                    &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2, &st->chash3, &st->cid2, &st->uniq,
-                    &st->sctl, &st->sdefer, &st->sbig,
-                    &st->del_off, &st->del_vert};
+  if (st->sub_slot >= 0) {
+    st->sub_thread.join();
+    st->sub_slot = -1;
+  }
+  DevBuf* bufs[] = {&st->rp[0], &st->rp[1], &st->rp[2], &st->col[0], &st->col[1], &st->col[2], &st->bsrc, &st->bdst,
+                    &st->keys, &st->idx, &st->keys2, &st->idx2, &st->keep, &st->pos, &st->eu, &st->ev, &st->hkeys,
+                    &st->hidx, &st->hkeys2, &st->hidx2, &st->dkeys, &st->didx, &st->dkeys2, &st->didx2, &st->degw,
+                    &st->p, &st->x, &st->words, &st->gwords, &st->off, &st->goff, &st->stats, &st->arena, &st->gids,
+                    &st->order, &st->bad, &st->cand_off, &st->cand_vert, &st->cand_hash, &st->cand_id, &st->chash2,
+                    &st->chash3, &st->cid2, &st->uniq, &st->sctl, &st->sdefer, &st->sbig};
   for (DevBuf* b : bufs) b->release();
+  for (BatchSlot& b : st->slot)
+    for (DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.del_off, &b.del_vert}) d->release();
   st->ew.release();
-  if (st->scan_tmp) (void)hipFree(st->scan_tmp);
-  if (st->sort_tmp) (void)hipFree(st->sort_tmp);
-  st->scan_tmp = st->sort_tmp = nullptr;
+  for (void** t : {&st->scan_tmp, &st->sort_tmp, &st->sort_tmp_b})
+    if (*t) (void)hipFree(*t);
+  st->scan_tmp = st->sort_tmp = st->sort_tmp_b = nullptr;
+  if (st->sub_stream) (void)hipStreamDestroy(st->sub_stream);
+  st->sub_stream = nullptr;
 }
 
 }  // namespace
@@ -1211,6 +1462,11 @@ int imce_create(const mce_csr* g, const mce_opts* opts, imce_state** out, mce_re
     if (hipMemcpyAsync(st->rp[0].p, &z, 8, hipMemcpyHostToDevice, s) != hipSuccess) return fail(MCE_EDEVICE);
   }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(MCE_EDEVICE);
+  // the subsumed pass of a submitted batch runs on a stream of its own
+  if (hipStreamCreateWithFlags(&st->sub_stream, hipStreamNonBlocking) != hipSuccess) {
+    set_error("hipStreamCreateWithFlags failed");
+    return fail(MCE_EDEVICE);
+  }
   mce_csr dg{n, st->rp[0].as<uint64_t>(), st->col[0].as<uint32_t>(), 1};
   mce_result r;
   rc = mce_static(&dg, MCE_RANK_DEGREE, &st->opts, &r, nullptr, nullptr);
@@ -1238,6 +1494,40 @@ int imce_remove_edges(imce_state* st, const uint32_t* src, const uint32_t* dst, 
     return MCE_EINVAL;
   }
   return update_impl(st, src, dst, rho, on_device, out, new_cl, del_cl, true);
+}
+
+int imce_submit(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t rho, int on_device, int remove) {
+  if (!st) {
+    set_error("NULL state");
+    return MCE_EINVAL;
+  }
+  return submit_impl(st, src, dst, rho, on_device, remove != 0);
+}
+
+int imce_collect(imce_state* st, imce_result* out, mce_clique_buf* new_cl, mce_clique_buf* del_cl) {
+  if (!st || !out) {
+    set_error("NULL state or result");
+    return MCE_EINVAL;
+  }
+  return collect_impl(st, out, new_cl, del_cl);
+}
+
+int imce_device_bytes(const imce_state* st, uint64_t* bytes) {
+  if (!st || !bytes) {
+    set_error("NULL state or output");
+    return MCE_EINVAL;
+  }
+  *bytes = state_bytes(st);
+  return MCE_OK;
+}
+
+int imce_batch_bytes(const imce_state* st, uint64_t rho, uint64_t* bytes) {
+  if (!st || !bytes) {
+    set_error("NULL state or output");
+    return MCE_EINVAL;
+  }
+  *bytes = batch_bytes(st, rho);
+  return MCE_OK;
 }
 
 int imce_info(const imce_state* st, uint64_t* n, uint64_t* nnz, uint64_t* count, uint64_t* set_hash) {

@@ -58,6 +58,8 @@ enum {
   CTL_HASH = 99,     // sum of clique hashes
   CTL_NODES = 100,   // search nodes
   CTL_OPS = 101,     // algorithmic 32-bit integer operations
+  CTL_OPS_EXEC = 102,   // the same at the executed row width
+  CTL_LDS_BYTES = 103,  // algorithmic LDS bytes
   CTL_DIAG = 104,    // 8 diagnostic counters (see mce_result.diag)
   CTL_WORDS = 128
 };

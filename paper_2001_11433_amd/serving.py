@@ -1,14 +1,21 @@
-"""Online IMCE serving: edge-addition batches handled as they arrive.
+"""Online IMCE serving: edge-addition (and deletion) batches handled as they arrive.
 
 Each session owns a device-resident incremental state (graph, clique count
 and set hash) and a HIP stream of its own.  Requests (session, batch) enter a
 pending queue with their arrival time.  The admission loop starts a request
-when (a) its session has no batch in flight (batches of one stream are
-causally ordered), (b) a slot is free, and (c) its memory estimate fits the
-budget; admitted requests run concurrently on worker threads, one per slot,
-each driving its session's stream, so their kernels overlap on the device.
-As soon as a request finishes its slot and memory return and the next
-eligible request is admitted: continuous batching across sessions.
+when (a) its session has room for it (one batch at a time, or two in
+pipelined mode), (b) a slot is free, and (c) the device memory of all states
+(as each state reports it, `imce_device_bytes`) plus what the batches in
+flight and this one are expected to add stays within the budget; a request
+that fails (c) while others are in flight waits and is counted as refused.
+Admitted requests run concurrently on worker threads, each driving its
+session's stream, so their kernels overlap on the device: continuous
+batching across sessions.
+
+Pipelined mode (Section 5's two steps per batch): a session's worker submits
+batch k+1 (its new-clique search) while batch k's subsumed-clique pass is
+still running on the state's second stream, then collects batch k
+(`imce_submit` / `imce_collect`).
 
 Latency = completion - arrival (queueing included); p50/p99 by nearest rank.
 """
@@ -19,7 +26,7 @@ import math
 import queue
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -33,11 +40,14 @@ class Request:
     seq: int
     src: np.ndarray
     dst: np.ndarray
+    remove: bool = False
     arrival: float = 0.0
     start: float = 0.0
     end: float = 0.0
     result: Optional[dict] = None
     error: Optional[str] = None
+    refused: int = 0  # times the memory check held it back
+    reserved: int = 0  # expected device-memory growth booked at admission
 
     @property
     def latency_ms(self) -> float:
@@ -52,14 +62,9 @@ def nearest_rank(values: Sequence[float], q: float) -> float:
     return float(v[k - 1])
 
 
-def estimate_bytes(rho: int) -> int:
-    """Device memory a batch may add beyond its session's resident state:
-    batch keys and sorts, edge subproblem tables and rows, clique buffers."""
-    return 256 * 1024 + rho * 4096
-
-
 class Server:
-    def __init__(self, graphs: Sequence, slots: int = 4, mem_budget: Optional[int] = None, **launch):
+    def __init__(self, graphs: Sequence, slots: int = 4, mem_budget: Optional[int] = None, pipeline: bool = False,
+                 **launch):
         torch = _torch()
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in graphs]
@@ -73,17 +78,40 @@ class Server:
             free, _total = torch.cuda.mem_get_info()
             mem_budget = int(free * 0.5)
         self.mem_budget = mem_budget
+        self.pipeline = pipeline
+        self.window = 2 if pipeline else 1  # batches of one session admitted at once
         self.lock = threading.Condition()
         self.pending: List[Request] = []
-        self.busy_sessions = set()
+        self.outstanding = [0] * len(graphs)
         self.in_flight = 0
-        self.mem_in_use = 0
         self.done: List[Request] = []
         self.max_in_flight = 0
         self.max_overlap_sessions = 0
+        self.refusals = 0
         self.on_done = None  # called with each finished request, under the lock
+        # memory model: the bytes each state holds and what a batch may add
+        # to it, both as the library reports them
+        self.state_bytes = [st.device_bytes() for st in self.states]
+        # each session's estimate for a batch of up to rho_ref edges, refreshed
+        # by the thread driving the state after each of its batches (the state
+        # is only ever queried by that thread while it serves)
+        self.rho_ref = [8192] * len(graphs)
+        self.growth = [st.batch_bytes(8192) for st in self.states]
+        self.reserved = 0  # expected growth of the admitted requests
+        self.max_bytes_seen = sum(self.state_bytes)
+        self.queues = [queue.Queue() for _ in graphs]
+        self.workers = []
+        if pipeline:
+            for s in range(len(graphs)):
+                t = threading.Thread(target=self._session_worker, args=(s,), daemon=True)
+                t.start()
+                self.workers.append(t)
 
     def close(self):
+        for q in self.queues:
+            q.put(None)
+        for t in self.workers:
+            t.join()
         for s in self.states:
             s.close()
 
@@ -93,39 +121,105 @@ class Server:
             self.pending.append(req)
             self.lock.notify_all()
 
+    def expected_growth(self, req: Request) -> int:
+        s = req.session
+        if len(req.src) > self.rho_ref[s]:  # a larger batch than the estimate covers: scale it up
+            return int(self.growth[s] * len(req.src) / self.rho_ref[s])
+        return self.growth[s]
+
     def _eligible(self) -> Optional[Request]:
-        # oldest pending request whose session is idle and whose estimate fits
+        # the oldest pending request whose session has room and no older batch
+        # pending (batches of a session run in order),
+        # whose expected memory fits the budget (always when nothing runs)
         for i, r in enumerate(self.pending):
-            if r.session in self.busy_sessions:
+            if self.outstanding[r.session] >= self.window:
                 continue
-            need = estimate_bytes(len(r.src))
-            if self.mem_in_use + need > self.mem_budget and self.in_flight > 0:
+            if any(p.session == r.session and p.seq < r.seq for p in self.pending):
                 continue
-            # keep per-session order: no older pending request of the same session
-            if any(p.session == r.session and p.seq < r.seq for p in self.pending[:i]):
+            total = sum(self.state_bytes) + self.reserved + self.expected_growth(r)
+            if total > self.mem_budget and self.in_flight > 0:
+                r.refused += 1
+                self.refusals += 1
                 continue
             return self.pending.pop(i)
         return None
 
-    def _run(self, req: Request):
-        torch = self.torch
-        st = self.states[req.session]
-        try:
-            with torch.cuda.stream(self.streams[req.session]):
-                req.start = time.perf_counter()
-                req.result = st.add(req.src, req.dst)
-                req.end = time.perf_counter()
-        except Exception as e:  # reported per request
-            req.error = repr(e)
-            req.end = time.perf_counter()
+    def _finish(self, req: Request, bytes_before: int, bytes_after: int, growth: int):
         with self.lock:
-            self.busy_sessions.discard(req.session)
+            self.rho_ref[req.session] = max(self.rho_ref[req.session], len(req.src))
+            self.growth[req.session] = growth
+            self.outstanding[req.session] -= 1
             self.in_flight -= 1
-            self.mem_in_use -= estimate_bytes(len(req.src))
+            self.reserved -= req.reserved
+            s = req.session
+            self.state_bytes[s] = bytes_after
+            self.max_bytes_seen = max(self.max_bytes_seen, sum(self.state_bytes))
             self.done.append(req)
             if self.on_done is not None:
                 self.on_done(req)
             self.lock.notify_all()
+
+    def _run(self, req: Request):
+        # one request start to end (imce_add_edges / imce_remove_edges)
+        torch = self.torch
+        st = self.states[req.session]
+        before = self.state_bytes[req.session]
+        try:
+            with torch.cuda.stream(self.streams[req.session]):
+                req.start = time.perf_counter()
+                req.result = st.remove(req.src, req.dst) if req.remove else st.add(req.src, req.dst)
+                req.end = time.perf_counter()
+        except Exception as e:  # reported per request
+            req.error = repr(e)
+            req.end = time.perf_counter()
+        self._finish(req, before, st.device_bytes(),
+                     st.batch_bytes(max(self.rho_ref[req.session], len(req.src))))
+
+    def _session_worker(self, s: int):
+        # pipelined: submit the next admitted batch before collecting the
+        # previous one, so its search overlaps the previous subsumed pass
+        torch = self.torch
+        st = self.states[s]
+        q = self.queues[s]
+        held = None  # submitted, not collected
+        before = self.state_bytes[s]
+
+        def collect(r):
+            nonlocal before
+            try:
+                r.result = st.collect()
+            except Exception as e:
+                r.error = repr(e)
+            r.end = time.perf_counter()
+            after = st.device_bytes()
+            self._finish(r, before, after, st.batch_bytes(max(self.rho_ref[s], len(r.src))))
+            before = after
+
+        with torch.cuda.stream(self.streams[s]):
+            while True:
+                r = q.get()
+                if r is None:
+                    break
+                r.start = time.perf_counter()
+                try:
+                    st.submit(r.src, r.dst, remove=r.remove)
+                except Exception as e:
+                    r.error = repr(e)
+                    r.end = time.perf_counter()
+                    if held is not None:
+                        collect(held)
+                        held = None
+                    self._finish(r, before, st.device_bytes(),
+                                 st.batch_bytes(max(self.rho_ref[s], len(r.src))))
+                    continue
+                if held is not None:
+                    collect(held)
+                held = r
+                if q.empty():
+                    collect(held)
+                    held = None
+            if held is not None:
+                collect(held)
 
     def serve(self, total: int, poll_s: float = 0.0005):
         """Admits and runs requests until `total` have completed."""
@@ -137,14 +231,19 @@ class Server:
                     r = self._eligible()
                     if r is None:
                         break
-                    self.busy_sessions.add(r.session)
+                    r.reserved = self.expected_growth(r)
+                    self.reserved += r.reserved
+                    self.outstanding[r.session] += 1
                     self.in_flight += 1
-                    self.mem_in_use += estimate_bytes(len(r.src))
                     self.max_in_flight = max(self.max_in_flight, self.in_flight)
-                    self.max_overlap_sessions = max(self.max_overlap_sessions, len(self.busy_sessions))
-                    t = threading.Thread(target=self._run, args=(r,), daemon=True)
-                    t.start()
-                    workers.append(t)
+                    self.max_overlap_sessions = max(self.max_overlap_sessions,
+                                                    sum(1 for o in self.outstanding if o > 0))
+                    if self.pipeline:
+                        self.queues[r.session].put(r)
+                    else:
+                        t = threading.Thread(target=self._run, args=(r,), daemon=True)
+                        t.start()
+                        workers.append(t)
                     started = True
                 if not started:
                     self.lock.wait(timeout=poll_s)
@@ -154,20 +253,22 @@ class Server:
 
 
 def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.ndarray]]], slots: int = 4,
-           rate_hz: Optional[float] = None, seed: int = 0, **launch) -> Dict[str, object]:
+           rate_hz: Optional[float] = None, seed: int = 0, pipeline: bool = False, mem_budget: Optional[int] = None,
+           removes: Optional[Sequence[Sequence[bool]]] = None, **launch) -> Dict[str, object]:
     """Serves every session's batch stream.  rate_hz=None: closed loop (each
-    session submits its next batch when the previous one completes); else
-    open loop with Poisson arrivals at rate_hz over all sessions.  `launch`
-    holds ImceState launch settings (waves_per_cu, donate_interval, ...)."""
-    srv = Server(graphs, slots=slots, **launch)
-    reqs = [Request(s, k, np.asarray(a, np.uint32), np.asarray(b, np.uint32))
+    session keeps one batch outstanding, two when pipelined: the next batch
+    arrives when one completes); else open loop with Poisson arrivals at
+    rate_hz over all sessions.  `removes[s][k]` marks batch k of session s as
+    a deletion.  `launch` holds ImceState launch settings."""
+    srv = Server(graphs, slots=slots, mem_budget=mem_budget, pipeline=pipeline, **launch)
+    reqs = [Request(s, k, np.asarray(a, np.uint32), np.asarray(b, np.uint32),
+                    remove=bool(removes[s][k]) if removes is not None else False)
             for s, stream in enumerate(streams) for k, (a, b) in enumerate(stream)]
     total = len(reqs)
     t0 = time.perf_counter()
     if rate_hz is None:
-        # closed loop: each session issues its next batch the moment the
-        # previous one completes, so a latency is one batch's own service time
-        # plus any wait for a slot shared with other sessions
+        # closed loop: each session issues its next batch the moment one of
+        # its outstanding batches completes
         nxt = {}
         for r in reqs:
             nxt.setdefault(r.session, []).append(r)
@@ -183,9 +284,11 @@ def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.nda
 
         srv.on_done = follow
         for q in nxt.values():
-            r = q.pop(0)
-            r.arrival = t0
-            srv.submit(r)
+            for _ in range(srv.window):
+                if q:
+                    r = q.pop(0)
+                    r.arrival = t0
+                    srv.submit(r)
         done = srv.serve(total)
     else:
         rng = np.random.default_rng(seed)
@@ -210,15 +313,19 @@ def replay(graphs: Sequence, streams: Sequence[Sequence[Tuple[np.ndarray, np.nda
     out = {"requests": done, "wall_s": wall, "p50_ms": nearest_rank(lat, 50), "p99_ms": nearest_rank(lat, 99),
            "mean_ms": float(np.mean(lat)) if lat else float("nan"), "errors": [r.error for r in done if r.error],
            "max_in_flight": srv.max_in_flight, "max_overlap_sessions": srv.max_overlap_sessions,
-           "throughput_batches_per_s": len(done) / wall if wall > 0 else 0.0}
+           "throughput_batches_per_s": len(done) / wall if wall > 0 else 0.0,
+           "refusals": srv.refusals, "refused_requests": sum(1 for r in done if r.refused),
+           "max_device_bytes": srv.max_bytes_seen, "mem_budget": srv.mem_budget}
     srv.close()
     return out
 
 
-def run_alone(g, stream: Sequence[Tuple[np.ndarray, np.ndarray]], **launch) -> List[dict]:
+def run_alone(g, stream: Sequence[Tuple[np.ndarray, np.ndarray]], removes: Optional[Sequence[bool]] = None,
+              **launch) -> List[dict]:
     """The same batches, one at a time, on a fresh state (reference results)."""
     st = ImceState(g, **launch)
-    out = [st.add(a, b) for a, b in stream]
+    out = [st.remove(a, b) if (removes is not None and removes[k]) else st.add(a, b)
+           for k, (a, b) in enumerate(stream)]
     st.close()
     return out
 

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_strerror_names_every_code():
     import paper_2001_11433_amd as m
     L = m.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         s = L.mce_strerror(code).decode()
         assert s and s != "unknown error"
 

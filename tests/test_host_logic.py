@@ -21,9 +21,45 @@ def test_tuner_signature_tracks_the_graph():
     assert tuner.signature(a, "degree") != tuner.signature(a, "degeneracy")
 
 
-def test_memory_estimate_grows_with_batch():
-    from paper_2001_11433_amd.serving import estimate_bytes
-    assert estimate_bytes(5000) > estimate_bytes(1000) > 0
+def _server_without_device(state_bytes, budget, window=1):
+    # the admission policy alone: a Server whose states are replaced by the
+    # byte counts they would report
+    import threading
+    from paper_2001_11433_amd.serving import Server
+    srv = object.__new__(Server)
+    srv.mem_budget, srv.window = budget, window
+    srv.lock = threading.Condition()
+    srv.pending, srv.done = [], []
+    srv.outstanding = [0] * len(state_bytes)
+    srv.in_flight, srv.refusals, srv.reserved = 0, 0, 0
+    srv.state_bytes = list(state_bytes)
+    srv.growth = [4096 * 1000] * len(state_bytes)  # what each state reports for a batch
+    srv.rho_ref = [8192] * len(state_bytes)
+    return srv
+
+
+def test_admission_by_reported_device_memory():
+    from paper_2001_11433_amd.serving import Request
+    e = np.zeros(1000, np.uint32)
+    srv = _server_without_device([100 << 20, 100 << 20], budget=(200 << 20) + 4096 * 1500)
+    a, b = Request(0, 0, e, e), Request(1, 0, e, e)
+    srv.pending += [a, b]
+    assert srv._eligible() is a  # fits: 200 MiB held + 4 MB expected
+    srv.in_flight, srv.outstanding[0], srv.reserved = 1, 1, srv.expected_growth(a)
+    assert srv._eligible() is None  # b would exceed the budget while a runs: refused
+    assert b.refused == 1 and srv.refusals == 1
+    srv.in_flight, srv.outstanding[0], srv.reserved = 0, 0, 0
+    assert srv._eligible() is b  # nothing in flight: always admitted
+    # a session never has more batches admitted than its window, and its
+    # batches are admitted in order
+    srv2 = _server_without_device([0], budget=1 << 40, window=2)
+    r0, r1, r2 = (Request(0, k, e, e) for k in range(3))
+    srv2.pending += [r1, r0, r2]
+    assert srv2._eligible() is r0
+    srv2.outstanding[0] = 2
+    assert srv2._eligible() is None
+    srv2.outstanding[0] = 1
+    assert srv2._eligible() is r1
 
 
 def test_tuned_knobs_are_accepted_by_every_entry_point():

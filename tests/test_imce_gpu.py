@@ -157,3 +157,113 @@ def test_powerlaw_stream_counts(m):
         want = ost.add(s, d)
         for k in ("n_applied", "n_skipped", "n_new", "n_del", "hash_new", "hash_del", "count", "set_hash"):
             assert got[k] == want[k], k
+
+
+KEYS = ("n_applied", "n_skipped", "n_new", "n_del", "hash_new", "hash_del", "count", "set_hash")
+
+
+def test_pipelined_batches_equal_one_at_a_time(m):
+    # imce_submit / imce_collect (batch k+1's search overlapping batch k's
+    # subsumed pass) give exactly the results of imce_add_edges /
+    # imce_remove_edges one batch at a time, additions and deletions mixed
+    g = gg.plant_communities(gg.chung_lu(20_000, 2.2, 12, seed=31), count=20, smin=20, smax=40, p=0.8, seed=32)
+    adds = gg.edge_stream(g, 6, 500, 3000, seed=33)
+    dels = gg.deletion_stream(g, 3, 200, 1500, seed=34, junk_fraction=0.1)
+    ops = [(a, False) for a in adds[:3]] + [(dels[0], True)] + [(a, False) for a in adds[3:5]] + \
+          [(dels[1], True), (dels[2], True), (adds[5], False)]
+    seq = m.ImceState(g)
+    want = [seq.remove(*b, cliques=True) if rm else seq.add(*b, cliques=True) for b, rm in ops]
+    seq.close()
+    st = m.ImceState(g)
+    got = []
+    st.submit(*ops[0][0], remove=ops[0][1])
+    for b, rm in ops[1:]:
+        st.submit(*b, remove=rm)
+        got.append(st.collect(cliques=True))
+    got.append(st.collect(cliques=True))
+    for k, (r, w) in enumerate(zip(got, want)):
+        for key in KEYS:
+            assert r[key] == w[key], (k, key)
+        assert r["new"] == w["new"] and r["del"] == w["del"], k
+    assert st.info()["count"] == want[-1]["count"]
+    st.close()
+
+
+def test_pipeline_call_rules(m):
+    import paper_2001_11433_amd as mod
+    g = gg.chung_lu(5000, 2.2, 10, seed=35)
+    b = gg.edge_stream(g, 3, 100, 200, seed=36)
+    st = m.ImceState(g)
+    with pytest.raises(mod.MceError) as e:
+        st.collect()
+    assert e.value.code == mod.MCE_EINVAL
+    st.submit(*b[0])
+    st.submit(*b[1])
+    with pytest.raises(mod.MceError) as e:
+        st.submit(*b[2])  # two uncollected already
+    assert e.value.code == mod.MCE_EINVAL
+    with pytest.raises(mod.MceError) as e:
+        st.add(*b[2])  # the one-shot call is refused while batches are pending
+    assert e.value.code == mod.MCE_EINVAL
+    r0, r1 = st.collect(), st.collect()
+    ref = m.ImceState(g)
+    w0, w1 = ref.add(*b[0]), ref.add(*b[1])
+    assert [r0[k] for k in KEYS] == [w0[k] for k in KEYS] and [r1[k] for k in KEYS] == [w1[k] for k in KEYS]
+    ref.close()
+    st.close()
+
+
+def _complete_batch(n, base):
+    iu, ju = np.triu_indices(n, 1)
+    return (iu + base).astype(np.uint32), (ju + base).astype(np.uint32)
+
+
+def test_pipeline_failure_rolls_back_and_drops_the_next_batch(m):
+    # a batch that makes K_30 out of 30 isolated vertices: the new clique holds
+    # 435 batch edges, beyond what the subsumed pass supports (MCE_ENOTSUP),
+    # which it reports only when its pass has run
+    import paper_2001_11433_amd as mod
+    g = gg.disjoint_union(gg.edgeless(30), gg.chung_lu(3000, 2.2, 10, seed=37))
+    st = m.ImceState(g)
+    before = st.info()
+    with pytest.raises(mod.MceError) as e:
+        st.add(*_complete_batch(30, 0))
+    assert e.value.code == mod.MCE_ENOTSUP and st.info() == before
+    later = gg.edge_stream(g, 1, 50, 50, seed=38)[0]
+    st.submit(*_complete_batch(30, 0))
+    with pytest.raises(mod.MceError) as e:
+        st.submit(*later)  # joins the failed pass: dropped
+    assert e.value.code == mod.MCE_ECANCELED
+    with pytest.raises(mod.MceError) as e:
+        st.collect()
+    assert e.value.code == mod.MCE_ENOTSUP
+    assert st.info() == before  # graph, count and hash as before the failed batch
+    r = st.add(*later)
+    ref = m.ImceState(g)
+    w = ref.add(*later)
+    assert [r[k] for k in KEYS] == [w[k] for k in KEYS]
+    ref.close()
+    st.close()
+
+
+def test_pipeline_collect_with_small_buffers_can_be_retried(m):
+    import ctypes
+    import torch
+    import paper_2001_11433_amd as mod
+    g = gg.chung_lu(5000, 2.2, 10, seed=39)
+    b = gg.edge_stream(g, 1, 300, 300, seed=40)[0]
+    st = m.ImceState(g)
+    st.submit(*b)
+    res = mod._ImceResult()
+    off = torch.zeros(2, dtype=torch.int64, device="cuda")
+    vert = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cb = mod._CliqueBuf(1, 1, off.data_ptr(), vert.data_ptr(), 1, 0, 0)
+    rc = mod.lib().imce_collect(st._h, ctypes.byref(res), ctypes.byref(cb), None)
+    assert rc == mod.MCE_ENOSPC and cb.n_cliques == res.n_new > 1
+    r = st.collect(cliques=True)  # the same batch, now with room
+    ref = m.ImceState(g)
+    w = ref.add(*b, cliques=True)
+    assert r["new"] == w["new"] and r["del"] == w["del"]
+    assert [r[k] for k in KEYS] == [w[k] for k in KEYS]
+    ref.close()
+    st.close()

@@ -72,3 +72,40 @@ def test_each_result_is_the_same_alone_and_in_the_mix(m):
         assert mix["max_overlap_sessions"] >= 2
         assert mix["p99_ms"] >= mix["p50_ms"] > 0
 
+
+
+def test_pipelined_serving_matches_alone(m):
+    # a session's next batch searched while its previous subsumed pass runs:
+    # every result still equals the batch processed alone
+    from paper_2001_11433_amd import serving
+    graphs, streams = _sessions()
+    removes = [[k % 3 == 2 for k in range(len(st))] for st in streams]
+    alone = [serving.run_alone(g, st, removes=rm) for g, st, rm in zip(graphs, streams, removes)]
+    for rate in (None, 400.0):
+        mix = serving.replay(graphs, streams, slots=4, rate_hz=rate, pipeline=True, removes=removes)
+        assert not mix["errors"]
+        for r in mix["requests"]:
+            want = alone[r.session][r.seq]
+            for k in serving.RESULT_KEYS:
+                assert r.result[k] == want[k], (rate, r.session, r.seq, k)
+
+
+def test_admission_refuses_what_the_budget_cannot_hold(m):
+    # a budget of one byte above what the fresh states hold: no second batch
+    # ever fits beside a running one, so requests are held back (counted) and
+    # run one at a time, and every result is unchanged
+    from paper_2001_11433_amd import serving
+    graphs, streams = _sessions()
+    alone = [serving.run_alone(g, st) for g, st in zip(graphs, streams)]
+    fresh = [m.ImceState(g) for g in graphs]
+    budget = sum(st.device_bytes() for st in fresh) + 1
+    assert all(st.batch_bytes(400) > 0 for st in fresh)
+    for st in fresh:
+        st.close()
+    mix = serving.replay(graphs, streams, slots=3, mem_budget=budget)
+    assert not mix["errors"]
+    assert mix["refusals"] > 0 and mix["refused_requests"] > 0
+    assert mix["max_in_flight"] == 1
+    for r in mix["requests"]:
+        for k in serving.RESULT_KEYS:
+            assert r.result[k] == alone[r.session][r.seq][k]
