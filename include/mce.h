@@ -124,7 +124,12 @@ typedef struct {
   /* Order of the handed-off nodes in the compact kernel's queue: 0 = as
    * produced, 1 = largest candidate set first.  Never changes results. */
   uint32_t compact_order;
-  uint32_t reserved[1];
+  /* Bit rows of a wide subproblem (over 64 candidates) in LDS: per-wave row
+   * cache of this many 64-bit words (0 = none, at most 4096).  A subproblem
+   * whose rows over its candidate columns fit ((|cand| + |relevant fini|) *
+   * ceil(|cand|/64) words) is searched from LDS, a wider one from device
+   * memory (the width classes of the search).  Never changes results. */
+  uint32_t lds_row_words;
 } mce_opts;
 
 typedef struct {

@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
                 ("sched_cost", ctypes.c_void_p), ("waves_per_cu", ctypes.c_uint32),
                 ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32), ("split", ctypes.c_uint32),
                 ("compact_waves_per_cu", ctypes.c_uint32), ("inline_compact", ctypes.c_uint32),
-                ("compact_order", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 1)]
+                ("compact_order", ctypes.c_uint32), ("lds_row_words", ctypes.c_uint32)]
 
 
 class _Result(ctypes.Structure):
@@ -181,7 +181,8 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0, donate_interval=0,
-          frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False, compact_order=0) -> _Opts:
+          frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False, compact_order=0,
+          lds_row_words=0) -> _Opts:
     o = _Opts()
     o.sched = SCHEDS[sched]
     o.validate = int(bool(validate))
@@ -194,6 +195,7 @@ def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0
     o.compact_waves_per_cu = int(compact_waves_per_cu)
     o.inline_compact = int(bool(inline_compact))
     o.compact_order = int(compact_order)
+    o.lds_row_words = int(lds_row_words)
     return o
 
 
@@ -205,7 +207,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
                validate: bool = False, stream=None, cost=None, waves_per_cu: int = 0, donate_interval: int = 0,
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
                split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False,
-               compact_order: int = 0, size_hist: int = 0, noalloc: bool = False) -> Dict[str, object]:
+               compact_order: int = 0, size_hist: int = 0, noalloc: bool = False,
+               lds_row_words: int = 0) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
@@ -220,7 +223,7 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     dg = _as_device_graph(g)
     csr = dg.csr()
     o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split, compact_waves_per_cu,
-              inline_compact, compact_order)
+              inline_compact, compact_order, lds_row_words)
     entry = lib().mce_static_noalloc if noalloc else lib().mce_static
     res = _Result()
     pv = None
@@ -301,14 +304,14 @@ class ImceState:
     request, the new and subsumed cliques as sorted lists of sorted tuples."""
 
     def __init__(self, g, stream=None, waves_per_cu: int = 0, donate_interval: int = 0, compact_waves_per_cu: int = 0,
-                 inline_compact: bool = False, compact_order: int = 0):
+                 inline_compact: bool = False, compact_order: int = 0, lds_row_words: int = 0, frame_cap: int = 0):
         torch = _torch()
         self._torch = torch
         dg = _as_device_graph(g)
         self.n = dg.n
         self.stream = stream
-        self._opts = _opts("degree", False, stream, None, waves_per_cu, donate_interval, 0, 0, compact_waves_per_cu,
-                           inline_compact, compact_order)
+        self._opts = _opts("degree", False, stream, None, waves_per_cu, donate_interval, frame_cap, 0,
+                           compact_waves_per_cu, inline_compact, compact_order, lds_row_words)
         h = ctypes.c_void_p()
         res = _Result()
         csr = dg.csr()

@@ -313,6 +313,7 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
     a.cl_vert = j.cl_vert;
     a.hist = j.hist;
     a.hist_len = j.hist_len;
+    a.lds_rows = std::min<uint32_t>(opts.lds_row_words, kLdsRowsMax);
     a.emit_extra = (j.cl_vert || j.hist) ? 1u : 0u;
     a.cap_cliques = j.cap_cliques;
     a.cap_verts = j.cap_verts;

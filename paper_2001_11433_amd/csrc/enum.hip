@@ -885,12 +885,22 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
       const uint32_t F = 3 * wp + wf + wx + 1;
       const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp, O_XX = 3 * wp + wf, O_Z = O_XX + wx;
       const uint64_t nrow = (uint64_t)p + x;
-      const uint64_t* rowP = a.arena + readlane64(a.sub.off[s], 0);
-      const uint64_t* rowPX = rowP + (uint64_t)wp * nrow;
+      const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
+      const uint64_t* rowPX = rowG + (uint64_t)wp * nrow;
       const uint64_t* excl = rowPX + (uint64_t)p * wx;
       const uint64_t* F0 = excl + (uint64_t)p * wp;
       const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
       const uint32_t kroot = EXCL ? 2 : 1;
+      // width class: rows over the cand columns that fit the wave's LDS row
+      // cache are read from LDS for the whole task, wider ones from the arena
+      const uint64_t rwords = (uint64_t)wp * nrow;
+      const uint64_t* rowP = rowG;
+      if (rwords <= a.lds_rows && (p > 64 || x > 64)) {
+        uint64_t* cache = lds_stack + kLdsWords;
+        for (uint64_t k = lane; k < rwords; k += kWave) cache[k] = rowG[k];
+        __syncthreads();
+        rowP = cache;
+      }
 
       uint64_t* stk;
       uint32_t cap;
@@ -1346,7 +1356,7 @@ hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* h
 }
 
 hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s) {
-  const size_t lds = (size_t)kLdsWords * sizeof(uint64_t);
+  const size_t lds = ((size_t)kLdsWords + a.lds_rows) * sizeof(uint64_t);
   if (exclusion)
     hipLaunchKernelGGL(k_enum<true>, dim3(grid), dim3(64), lds, s, a);
   else

@@ -107,7 +107,11 @@ struct EnumArgs {
   uint64_t* hist;        // clique-size histogram (nullable), hist_len entries, last = hist_len - 1 or more
   uint64_t hist_len;
   uint32_t emit_extra;   // nonzero when cliques are written out or tallied by size (cl_vert or hist)
+  uint32_t lds_rows;     // 64-bit words of the per-wave LDS row cache of k_enum (0 = none)
 };
+
+// Largest per-wave LDS row cache (keeps k_enum's LDS below 64 KiB per workgroup).
+constexpr uint32_t kLdsRowsMax = 4096;
 
 // Sizes below this are tallied per wave in LDS and flushed at exit; larger
 // ones go to the histogram with device atomics.

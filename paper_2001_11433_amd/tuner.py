@@ -1,12 +1,17 @@
 """Autotuner for the persistent enumeration launch.
 
 The tunable knobs change only speed, never results: waves per compute unit
-(how many persistent wavefronts share the work queue) and the donation
-interval (search nodes between checks for idle waves).  Skewed graphs, where
-one subproblem holds most of the work, prefer few, quiet waves; graphs with
-many heavy subproblems prefer full occupancy.  The tuner runs a coordinate
-search (waves first, then interval) and keeps the fastest setting, checking
-that every trial returns the same count and hash.
+(how many persistent wavefronts share the work queue), the compact kernel's
+waves per CU (or the compact search in place), the donation interval (search
+nodes between checks for idle waves), the order of the compact phase, the
+width class boundary (the per-wave LDS row cache: subproblems whose bit rows
+fit it are searched from LDS, wider ones from device memory) and the initial
+DFS stack depth.  Skewed graphs, where one subproblem holds most of the work,
+prefer few, quiet waves; graphs with many heavy subproblems prefer full
+occupancy.  The tuner runs a grid over the two wave counts, then a coordinate
+search over the rest, timing each trial as the median of several runs, and
+keeps the fastest setting, checking that every trial returns the same count,
+hash and node count.
 
 Results are cached per graph signature (n, m, max degree, degree-sequence
 digest, rank) in a JSON table; `tuning.json` next to this file holds the
@@ -33,13 +38,17 @@ GRID = (
     ("compact", ("inline", 8, 12, 20, 28)),
     ("waves_per_cu", (2, 4, 8, 16)),
 )
-SPACE = (("donate_interval", (256, 1024, 4096, 16384)), ("compact_order", (0, 1)))
-DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20, "compact_order": 0}
+SPACE = (("donate_interval", (256, 1024, 4096, 16384)), ("compact_order", (0, 1)),
+         ("lds_row_words", (0, 1024, 2048, 4096)), ("frame_cap", (32, 128, 512)))
+DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20, "compact_order": 0, "lds_row_words": 0,
+           "frame_cap": 128}
+SAMPLES = 3
 
 
 def launch_kwargs(knobs: dict) -> dict:
     """Tuned knobs as mce_static keyword arguments."""
-    out = {"waves_per_cu": int(knobs.get("waves_per_cu", 0)), "donate_interval": int(knobs.get("donate_interval", 0))}
+    out = {"waves_per_cu": int(knobs.get("waves_per_cu", 0)), "donate_interval": int(knobs.get("donate_interval", 0)),
+           "lds_row_words": int(knobs.get("lds_row_words", 0)), "frame_cap": int(knobs.get("frame_cap", 0))}
     c = knobs.get("compact", DEFAULT["compact"])
     if c == "inline":
         out["inline_compact"] = True
@@ -81,10 +90,12 @@ def lookup(g, rank: str, path: str = TABLE, family: Optional[str] = None) -> dic
 
 
 def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, space=SPACE,
-         time_limit_s: Optional[float] = None, path: Optional[str] = TABLE, log=None) -> dict:
+         time_limit_s: Optional[float] = None, path: Optional[str] = TABLE, log=None, samples: int = SAMPLES,
+         key: Optional[str] = None) -> dict:
     """Grid over `grid`, then a coordinate search over `space` from the best
-    grid point; returns {"best": knobs, "enum_ms": t, "trials": [...]} and
-    records it under the graph's signature."""
+    grid point, each trial the median enumeration time of `samples` runs;
+    returns {"best": knobs, "enum_ms": t, "trials": [...]} and records it
+    under the graph's signature (or `key`)."""
     dg = _as_device_graph(g)
     trials = []
     ref = None
@@ -92,14 +103,17 @@ def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, s
 
     def run(knobs):
         nonlocal ref
-        r = mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(knobs))
-        key = (r["count"], r["set_hash"], r["nodes_total"])
-        if ref is None:
-            ref = key
-        elif key != ref:
-            raise RuntimeError("tuning trial changed the result: %r vs %r" % (key, ref))
-        t = r["enum_ms"]
-        trials.append(dict(knobs, enum_ms=t))
+        ts = []
+        for _ in range(samples):
+            r = mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(knobs))
+            got = (r["count"], r["set_hash"], r["nodes_total"])
+            if ref is None:
+                ref = got
+            elif got != ref:
+                raise RuntimeError("tuning trial changed the result: %r vs %r" % (got, ref))
+            ts.append(r["enum_ms"])
+        t = float(np.median(ts))
+        trials.append(dict(knobs, enum_ms=t, samples=ts))
         if log:
             log("tune %s enum_ms=%.1f" % (knobs, t))
         return t
@@ -127,10 +141,10 @@ def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, s
             t = run(k)
             if t < best_t:
                 best, best_t = k, t
-    result = {"best": best, "enum_ms": best_t, "trials": trials}
+    result = {"best": best, "enum_ms": best_t, "trials": trials, "samples": samples}
     if path:
         table = load_table(path)
-        table[signature(g, rank)] = result
+        table[key or signature(g, rank)] = result
         save_table(table, path)
     return result
 
@@ -200,3 +214,53 @@ def tune_imce(g, batches, start: Optional[dict] = None, space=IMCE_SPACE, path: 
         table[key or signature(g, "degree") + "-imce"] = result
         save_table(table, path)
     return result
+
+
+def tune_workloads(out_path: str = TABLE, which: Sequence[str] = ("rmat14", "rmat15", "cl500k", "cl1m-communities",
+                                                                  "cl500k-imce"), log=print) -> Dict[str, dict]:
+    """Tunes the launch of the benchmark workloads and records each under its
+    graph signature and its generator family ("family:<name>"): the R-MAT
+    family at scales 14 and 15 (degeneracy rank; scale 16 takes the scale-15
+    entry), the 500k-vertex Chung-Lu graph (degree rank, static and
+    incremental) and the 1M-vertex Chung-Lu graph with planted communities."""
+    import graphgen as gg
+    table = load_table(out_path)
+    done = {}
+    for name in which:
+        if name.startswith("rmat"):
+            scale = int(name[4:])
+            g, rank = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=0), "degeneracy"
+        elif name == "cl1m-communities":
+            g = gg.plant_communities(gg.chung_lu(1_000_000, 2.1, 20, seed=0), count=500, smin=30, smax=80, p=0.9,
+                                     seed=1)
+            rank = "degree"
+        else:
+            g, rank = gg.chung_lu(500_000, 2.2, 16, seed=0), "degree"
+        if name.endswith("-imce"):
+            batches = gg.edge_stream(g, 24, 1000, 5000, seed=2, triadic_fraction=0.5)
+            start = lookup(g, "degree", out_path, family="cl500k")
+            r = tune_imce(g, batches, start=start, path=out_path, log=log)
+            table = load_table(out_path)
+            table["family:" + name] = r
+        else:
+            r = tune(g, rank, path=out_path, log=log)
+            table = load_table(out_path)
+            table["family:" + name] = r
+            if name == "rmat15":
+                table["family:rmat16"] = r
+        save_table(table, out_path)
+        done[name] = r["best"]
+        log("tuned %s: %s" % (name, r["best"]))
+    return done
+
+
+if __name__ == "__main__":
+    import argparse
+    import shutil
+    ap = argparse.ArgumentParser(description="tune the benchmark workloads' launch settings")
+    ap.add_argument("--out", default=TABLE, help="table to update (a copy of the packaged one is made first)")
+    ap.add_argument("workloads", nargs="*", default=["rmat14", "rmat15", "cl500k", "cl1m-communities", "cl500k-imce"])
+    a = ap.parse_args()
+    if a.out != TABLE and not os.path.exists(a.out):
+        shutil.copyfile(TABLE, a.out)
+    tune_workloads(a.out, a.workloads)

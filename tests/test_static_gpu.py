@@ -311,3 +311,26 @@ def test_imbalance_shares_from_gpu_outputs(m):
     got = m.mce_static(g, rank="degeneracy", per_vertex=True)
     want = O.mce_parmce(g, "degeneracy", threads=8)
     assert D.imbalance(_u64(got["nodes_v"]), _u64(got["count_v"])) == D.imbalance(want.nodes_v, want.count_v)
+
+
+@pytest.mark.parametrize("words", [256, 1024, 4096])
+def test_lds_row_cache_width_classes(m, words):
+    # the same subproblems searched with their rows in the LDS row cache when
+    # they fit it (a class boundary of `words` 64-bit words) and from device
+    # memory when not: identical cliques, hashes and node counts
+    for g, rank in ((gg.disjoint_union(gg.complete(300), gg.er(200, 0.3, seed=4)), "degree"),
+                    (gg.er(150, 0.55, seed=5), "degeneracy"),
+                    (gg.plant_communities(gg.chung_lu(4000, 2.1, 10, seed=8), count=6, smin=70, smax=100, p=0.6,
+                                          seed=9), "degree")):
+        _check(m, g, rank, cliques=True, lds_row_words=words)
+        _check(m, g, rank, lds_row_words=words, waves_per_cu=2, donate_interval=16)
+
+
+def test_lds_row_cache_in_the_incremental_step(m):
+    from paper_2001_11433_amd import serving
+    g = gg.plant_communities(gg.chung_lu(5000, 2.2, 12, seed=10), count=5, smin=70, smax=100, p=0.6, seed=11)
+    stream = gg.edge_stream(g, 4, 200, 800, seed=12)
+    ref = serving.run_alone(g, stream)
+    got = serving.run_alone(g, stream, lds_row_words=2048)
+    for a, b in zip(ref, got):
+        assert [a[k] for k in serving.RESULT_KEYS] == [b[k] for k in serving.RESULT_KEYS]
