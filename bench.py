@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "maximal cliques/s (bit-exact set hash), learned vs plain sched; p99 update ms"
 INT32_VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s
+LDS_PEAK = 256 * 128 * 2.4e9  # bytes/s: 128 bytes per clock per CU
 
 
 def log(*a):
@@ -77,6 +78,56 @@ def cpu_baseline(g, rank: str, seconds: float, seed: int = 7):
             "kind": "oracle",
             "sample": "%d of %d subproblems in uniform random order (seed %d), %d cliques in %.1f s; the oracle's "
                       "rank metric and G_v construction are inside the timed region" % (done, g.n, seed, cliques, el)}
+
+
+def cpu_baseline_legs(g, rank: str, seconds: float, seed: int = 7):
+    """The other oracle legs: the per-vertex decomposition on one thread over
+    the same kind of random sample, and Algorithm 1 from the root (the paper's
+    sequential baseline) on the 2000-vertex ER graph, where it finishes."""
+    import graphgen as gg
+    import oracle
+    order = np.random.default_rng(seed).permutation(g.n).astype(np.uint32)
+    done = cliques = 0
+    t0 = time.perf_counter()
+    chunk = 1024
+    while done < g.n and time.perf_counter() - t0 < seconds:
+        sel = order[done:done + chunk]
+        cliques += oracle.mce_parmce(g, rank, verts=sel, threads=1).count
+        done += sel.size
+        chunk = min(chunk * 2, 1 << 16)
+    el = time.perf_counter() - t0
+    out = {"o2_one_thread": {"value": cliques / el if el > 0 else 0.0, "unit": "maximal cliques/s", "cores": 1,
+                             "kind": "oracle", "sample": "%d of %d subproblems in uniform random order (seed %d), "
+                             "%d cliques in %.1f s" % (done, g.n, seed, cliques, el)}}
+    er = gg.er(2000, 0.01, seed=0)
+    t0 = time.perf_counter()
+    c, h, nodes = oracle.mce_root(er)
+    el = time.perf_counter() - t0
+    out["o1_root_er2000"] = {"value": c / el, "unit": "maximal cliques/s", "cores": 1, "kind": "oracle",
+                             "sample": "Algorithm 1 from the root on er(n=2000, p=0.01, seed=0): %d cliques, hash "
+                                       "%016x, %d search nodes in %.2f s" % (c, h, nodes, el)}
+    return out
+
+
+def rmat_family(m, scales=(15, 16)):
+    """The R-MAT family (edge factor 16, .57/.19/.19/.05, seed 0, degeneracy
+    rank) at the largest scales one GPU enumerates in about a minute; scale
+    18 is out of reach (each scale multiplies the clique count by about 60)."""
+    import graphgen as gg
+    from paper_2001_11433_amd import tuner
+    out = []
+    for scale in scales:
+        g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=0)
+        dg = m.DeviceGraph.from_graph(g)
+        knobs = tuner.lookup(g, "degeneracy", family="rmat%d" % scale)
+        r = m.mce_static(dg, rank="degeneracy", **tuner.launch_kwargs(knobs))
+        dev_s = (r["rank_ms"] + r["build_ms"] + r["enum_ms"]) / 1e3
+        out.append({"scale": scale, "n": g.n, "m": g.m, "maximal_cliques": r["count"],
+                    "set_hash": "%016x" % r["set_hash"], "search_nodes": r["nodes_total"], "max_cand": r["max_cand"],
+                    "rank_ms": r["rank_ms"], "build_ms": r["build_ms"], "enum_ms": r["enum_ms"],
+                    "cliques_per_s": r["count"] / dev_s, "launch": knobs})
+        log("rmat scale %d: %d cliques in %.1f ms" % (scale, r["count"], r["enum_ms"]))
+    return out
 
 
 def _median(xs):
@@ -299,10 +350,43 @@ def serving(m, repeats: int = 3, loads=(0.5, 0.9)):
                            "max_overlap_sessions": r["max_overlap_sessions"]}
     log("serving two sessions: p50 %.2f p99 %.2f ms, %.1f batches/s" % (r["p50_ms"], r["p99_ms"],
                                                                           r["throughput_batches_per_s"]))
+    # pipelined: a batch's search overlaps the previous batch's subsumed pass
+    lat, walls = [], []
+    for i in range(repeats):
+        r = sv.replay([g], [stream], slots=2, rate_hz=None, pipeline=True, **launch)
+        if r["errors"]:
+            raise SystemExit("serving errors: %r" % r["errors"][:3])
+        finals.add((r["requests"][-1].result["count"], r["requests"][-1].result["set_hash"]))
+        lat += [q.latency_ms for q in r["requests"]]
+        walls.append(r["wall_s"])
+    out["pipelined_closed_loop"] = {"repeats": repeats, "window": 2, "p50_ms": sv.nearest_rank(lat, 50),
+                                    "p99_ms": sv.nearest_rank(lat, 99), "mean_ms": float(np.mean(lat)),
+                                    "batches_per_s": len(stream) / _median(walls)}
+    log("serving pipelined: p50 %.2f p99 %.2f ms, %.1f batches/s" % (
+        out["pipelined_closed_loop"]["p50_ms"], out["pipelined_closed_loop"]["p99_ms"],
+        out["pipelined_closed_loop"]["batches_per_s"]))
     if len(finals) != 1:
         raise SystemExit("serving runs disagree: %r" % finals)
     cnt, h = finals.pop()
     out["final_count"], out["final_set_hash"] = cnt, "%016x" % h
+    # deletions (Section 5.3): the stream's batches removed again in reverse
+    # order, which must lead back to the starting graph's clique set
+    from paper_2001_11433_amd import ImceState
+    st = ImceState(g, **launch)
+    start = (st.initial["count"], st.initial["set_hash"])
+    for a, b in stream:
+        st.add(a, b)
+    dl = []
+    for a, b in reversed(stream):
+        r = st.remove(a, b)
+        dl.append(r["ms"])
+    st.close()
+    if (r["count"], r["set_hash"]) != start:
+        raise SystemExit("deleting the stream did not restore the starting clique set")
+    out["deletions"] = {"batches": len(stream), "p50_ms": sv.nearest_rank(dl, 50), "p99_ms": sv.nearest_rank(dl, 99),
+                        "mean_ms": float(np.mean(dl)), "restored_count": start[0],
+                        "restored_set_hash": "%016x" % start[1], "note": "device time per deletion batch"}
+    log("deletions: p50 %.2f p99 %.2f ms (device)" % (out["deletions"]["p50_ms"], out["deletions"]["p99_ms"]))
     out["p99_update_ms"] = out["closed_loop"]["p99_ms"]
     return out
 
@@ -375,6 +459,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ownership", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-rmat-family", action="store_true")
     ap.add_argument("--learned-scale", type=int, default=14)
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--print-digest", action="store_true", help="print the search kernels' source digest and exit")
@@ -446,8 +531,22 @@ def main():
                      "traffic_unit": "bytes per call (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)",
                      "kernel": "k_enum + k_compact (the enumeration: both launches)",
                      "ops_per_launch": r0["alg_ops"],
-                     "issue": measured_issue()},
+                     "issue": measured_issue(),
+                     "executed_width": {"achieved": r0["exec_ops"] / enum_s / 1e12,
+                                        "frac": r0["exec_ops"] / enum_s / INT32_VALU_PEAK,
+                                        "ops_per_launch": r0["exec_ops"],
+                                        "note": "the same nodes at the row width the kernels execute (2 words "
+                                                "per row for compact nodes)"},
+                     "lds": {"achieved": r0["lds_bytes"] / enum_s / 1e9, "peak": LDS_PEAK / 1e9, "unit": "GB/s",
+                             "frac": r0["lds_bytes"] / enum_s / LDS_PEAK, "bytes_per_launch": r0["lds_bytes"],
+                             "note": "algorithmic: 4 * w * (s + |ext|) per node"}},
     }
+    from paper_2001_11433_amd import diagnostics
+    hs = m.mce_static(dg, rank=rank, sched=args.sched, size_hist=4097, **launch)
+    out["clique_sizes"] = diagnostics.size_distribution(hs["size_hist"])
+    if not args.no_rmat_family:
+        log("R-MAT family ...")
+        out["rmat_family"] = rmat_family(m)
     if not args.no_ownership:
         log("ownership ranks and imbalance ...")
         out["ownership"] = ownership_and_imbalance(m, dg, (r0["count"], r0["set_hash"]), launch, rank)
@@ -462,6 +561,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, rank, args.cpu_seconds)
+        out["cpu_baseline_legs"] = cpu_baseline_legs(g, rank, args.cpu_seconds / 2)
     print(json.dumps(out), flush=True)
 
 
