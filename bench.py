@@ -134,22 +134,55 @@ def _median(xs):
     return float(np.median(np.asarray(xs, dtype=np.float64)))
 
 
-def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 5, epochs: int = 400):
-    """Queue order by degree, by triangle count, by the MLP's predicted cost
-    (largest first) and, as the ceiling of any cost-based order, by the node
-    counts the enumeration itself measured, on held-out R-MAT graphs.
-    Ownership rank is degeneracy in every case, so cliques, hash and node
-    counts are identical across orders and only the time moves."""
+def _family(name: str):
+    """(description, rank, graph maker by seed) of a learned-scheduling family."""
+    import graphgen as gg
+    if name.startswith("rmat"):
+        scale = int(name[4:])
+        return ("rmat(scale=%d, edge_factor=16, abcd=.57/.19/.19/.05); degeneracy rank" % scale, "degeneracy",
+                lambda s: gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s))
+    if name == "cl1m-communities":
+        return ("chung_lu(1e6, 2.1, 20) + 500 communities U{30..80} p=0.9; degree rank", "degree",
+                lambda s: gg.plant_communities(gg.chung_lu(1_000_000, 2.1, 20, seed=2 * s),
+                                               count=500, smin=30, smax=80, p=0.9, seed=2 * s + 1))
+    raise ValueError(name)
+
+
+def _family_graph(args):
+    family, seed = args
+    return seed, _family(family)[2](seed)
+
+
+def pregenerate(family: str, seeds, workers: int = 12):
+    """The family's graphs built in a pool of forked host processes (run
+    before the GPU is first used: the children only generate graphs)."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(max(1, min(workers, len(seeds)))) as pool:
+        return dict(pool.map(_family_graph, [(family, s) for s in seeds]))
+
+
+def learned_sched(m, family: str, train_seeds, held_seeds, repeats: int = 3, epochs: int = 400,
+                  split: int = 64, graphs=None):
+    """Queue order by degree, by triangle count, by the cost model evaluated
+    inside the call (MCE_SCHED_MLP: features and BF16 inference overlap the
+    subproblem build), the same with the predicted-heavy roots dealt out at
+    launch (`split`), and, as the ceiling of any cost-based order, by the node
+    counts the enumeration itself measured (with and without the split), on
+    held-out graphs of the family.  Ownership is fixed per family, so cliques,
+    hash and node counts are identical across orders and only the time moves;
+    times are whole calls (rank, build, inference and search) on the device."""
     import torch
     from scipy.stats import spearmanr
-    import graphgen as gg
     from paper_2001_11433_amd import costmodel, tuner
 
-    fam = "rmat(scale=%d, edge_factor=16, abcd=.57/.19/.19/.05); degeneracy rank" % scale
+    fam, rank, make = _family(family)
+    if graphs is not None:
+        make = graphs.pop
     t0 = time.perf_counter()
-    train = [gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s) for s in train_seeds]
-    log("learned_sched: training on %d graphs" % len(train))
-    tr = costmodel.train_on_graphs(train, "degeneracy", epochs=epochs, lr=3e-3)
+    train = [make(s) for s in train_seeds]
+    log("learned_sched %s: training on %d graphs" % (family, len(train)))
+    tr = costmodel.train_on_graphs(train, rank, epochs=epochs, lr=3e-3)
+    del train
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     model = tr["model"]
@@ -157,68 +190,63 @@ def learned_sched(m, scale: int, train_seeds, held_seeds, repeats: int = 5, epoc
            "train": {"vertices": tr["n_train"], "epochs": epochs, "loss_first": tr["losses"][0],
                      "loss_last": tr["losses"][-1], "wall_s": train_s,
                      "kernels": "mce_mlp_grad + mce_mlp_adam (fp32)"},
-           "inference": "mce_features + mce_mlp_forward_bf16",
+           "inference": "inside mce_static (MCE_SCHED_MLP): mce_features' columns + BF16 forward on a second stream",
            "policies": {"degree": "vertex degree, largest first", "triangle": "triangles, largest first",
-                        "learned": "MLP-predicted log search nodes, largest first",
+                        "learned": "MLP-predicted log search nodes, largest first, evaluated in the call",
+                        "learned_split": "learned, and roots predicted above one wave's share split into up to "
+                                         "%d chunks at launch" % split,
                         "measured": "the subproblem's measured search nodes, largest first (ceiling of any "
-                                    "cost-based order)"},
+                                    "cost-based order)",
+                        "measured_split": "measured, with the same split"},
            "repeats": repeats, "held_out": []}
-    names = ("degree", "triangle", "learned", "measured")
+    names = ("degree", "triangle", "learned", "learned_split", "measured", "measured_split")
     tot_enum = dict.fromkeys(names, 0.0)
     tot_wall = dict.fromkeys(names, 0.0)
     cliques_total = 0
     for s in held_seeds:
-        g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, seed=s)
+        g = make(s)
         dg = m.DeviceGraph.from_graph(g)
-        knobs = tuner.lookup(g, "degeneracy", family="rmat%d" % scale)
+        knobs = tuner.lookup(g, rank, family=family)
         kw = tuner.launch_kwargs(knobs)
-        feat, target, base = costmodel.collect(dg, "degeneracy")
+        feat, target, base = costmodel.collect(dg, rank)
         pred = model.predict(feat)
         measured = target.float().contiguous()
         y, t = pred.cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
         ref = (base["count"], base["set_hash"], base["nodes_total"])
-        inf = []
-        for _ in range(repeats):
-            torch.cuda.synchronize()
-            w0 = time.perf_counter()
-            model.predict(m.mce_features(dg))
-            torch.cuda.synchronize()
-            inf.append((time.perf_counter() - w0) * 1e3)
         row = {"seed": s, "n": g.n, "m": g.m, "maximal_cliques": base["count"],
                "set_hash": "%016x" % base["set_hash"], "search_nodes": base["nodes_total"],
                "mse_log_nodes": float(np.mean((y - t) ** 2)), "spearman": float(spearmanr(y, t)[0]),
-               "inference_ms": _median(inf), "launch": knobs}
+               "spearman_degree": float(spearmanr(np.diff(g.row_ptr).astype(np.float64), t)[0]),
+               "launch": knobs}
+        del g
         for name in names:
-            enum, wall = [], []
+            enum, dev = [], []
             for _ in range(repeats):
-                torch.cuda.synchronize()
-                w0 = time.perf_counter()
-                if name == "learned":
-                    c = model.predict(m.mce_features(dg))
-                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=c, **kw)
-                elif name == "measured":
-                    r = m.mce_static(dg, rank="degeneracy", sched="cost", cost=measured, **kw)
+                if name.startswith("learned"):
+                    r = m.mce_static(dg, rank=rank, sched="mlp", model=model,
+                                     split=split if name.endswith("split") else 0, **kw)
+                elif name.startswith("measured"):
+                    r = m.mce_static(dg, rank=rank, sched="cost", cost=measured,
+                                     split=split if name.endswith("split") else 0, **kw)
                 else:
-                    r = m.mce_static(dg, rank="degeneracy", sched=name, **kw)
-                torch.cuda.synchronize()
-                wall.append((time.perf_counter() - w0) * 1e3)
+                    r = m.mce_static(dg, rank=rank, sched=name, **kw)
+                dev.append(r["rank_ms"] + r["build_ms"] + r["enum_ms"])
                 enum.append(r["enum_ms"])
                 got = (r["count"], r["set_hash"], r["nodes_total"])
                 if got != ref:
                     raise SystemExit("schedule %s changed the result on seed %d: (count, hash, nodes) %r, "
                                      "expected %r" % (name, s, got, ref))
-            row[name] = {"enum_ms": _median(enum), "wall_ms": _median(wall),
-                         "cliques_per_s": base["count"] / (_median(wall) / 1e3)}
+            row[name] = {"enum_ms": _median(enum), "call_ms": _median(dev),
+                         "cliques_per_s": base["count"] / (_median(dev) / 1e3)}
             tot_enum[name] += _median(enum)
-            tot_wall[name] += _median(wall)
+            tot_wall[name] += _median(dev)
         cliques_total += base["count"]
-        log("learned_sched seed %d: enum ms %s" % (s, {k: round(row[k]["enum_ms"], 1) for k in names}))
+        log("learned_sched %s seed %d: call ms %s" % (family, s, {k: round(row[k]["call_ms"], 1) for k in names}))
         out["held_out"].append(row)
+        del dg
     out["cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_wall.items()}
-    out["enum_cliques_per_s"] = {k: cliques_total / (v / 1e3) for k, v in tot_enum.items()}
-    out["gain_vs_degree"] = tot_wall["degree"] / tot_wall["learned"]
-    out["enum_gain_vs_degree"] = tot_enum["degree"] / tot_enum["learned"]
-    out["measured_enum_gain_vs_degree"] = tot_enum["degree"] / tot_enum["measured"]
+    out["gain_vs_degree"] = {k: tot_wall["degree"] / tot_wall[k] for k in names}
+    out["enum_gain_vs_degree"] = {k: tot_enum["degree"] / tot_enum[k] for k in names}
     return out
 
 
@@ -460,7 +488,10 @@ def main():
     ap.add_argument("--no-ownership", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rmat-family", action="store_true")
-    ap.add_argument("--learned-scale", type=int, default=14)
+    ap.add_argument("--learned-family", default="rmat15",
+                    help="graph family of the learned-scheduling comparison: rmat<scale> or cl1m-communities")
+    ap.add_argument("--learned-out", default=None,
+                    help="run only the learned-scheduling comparison and write its JSON here")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--print-digest", action="store_true", help="print the search kernels' source digest and exit")
     args = ap.parse_args()
@@ -472,10 +503,21 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    pre = None
+    if (not args.no_learned or args.learned_out) and args.learned_family == "cl1m-communities":
+        # before anything touches the GPU: the pool forks
+        log("generating the %s graphs" % args.learned_family)
+        pre = pregenerate(args.learned_family, list(range(1, 13)))
     import torch
     import paper_2001_11433_amd as m
     if not torch.cuda.is_available():
         raise SystemExit("no GPU")
+    if args.learned_out:
+        r = learned_sched(m, args.learned_family, range(1, 11), (11, 12), graphs=pre)
+        with open(args.learned_out, "w") as f:
+            json.dump(r, f, indent=1)
+        log("learned gain vs degree (whole call):", r["gain_vs_degree"])
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -553,7 +595,7 @@ def main():
         out["decompositions"] = decompositions(m)
     if not args.no_learned:
         log("learned scheduling ...")
-        out["learned_sched"] = learned_sched(m, args.learned_scale, range(1, 11), (11, 12))
+        out["learned_sched"] = learned_sched(m, args.learned_family, range(1, 11), (11, 12), graphs=pre)
     if not args.no_serving:
         log("serving ...")
         out["serving"] = serving(m)

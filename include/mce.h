@@ -96,7 +96,12 @@ typedef enum {
   MCE_SCHED_TRIANGLE = 1, /* triangles through the vertex */
   MCE_SCHED_COST = 2,     /* caller-supplied per-vertex float cost, any real value (e.g. a learned
                              model's predicted log search nodes) */
-  MCE_SCHED_ID = 3        /* ascending vertex id */
+  MCE_SCHED_ID = 3,       /* ascending vertex id */
+  MCE_SCHED_MLP = 4       /* the learned cost model, evaluated inside the call: the features of
+                             mce_features (core numbers and triangles reused when the rank already
+                             computed them) and the bfloat16 forward of mce_mlp_forward_bf16, on a
+                             second stream while the subproblems are built; the predicted log search
+                             nodes order the queue as MCE_SCHED_COST would, and drive `split` */
 } mce_sched;
 
 typedef struct {
@@ -130,6 +135,19 @@ typedef struct {
    * ceil(|cand|/64) words) is searched from LDS, a wider one from device
    * memory (the width classes of the search).  Never changes results. */
   uint32_t lds_row_words;
+  /* Device memory for the search's handoff records, in MiB (0 = 16384, at
+   * most 65536).  A node re-based for the compact kernel is written there as
+   * one small record (its subproblem, K and candidate masks; no row data);
+   * once the budget is used up, further nodes are searched in place by the
+   * first kernel, with the same results, more slowly.  This bounds the call's
+   * memory whatever the number of search nodes. */
+  uint32_t hand_mb;
+  /* MCE_SCHED_MLP: the cost model's parameter block (device memory,
+   * mce_mlp_param_count() floats, layout as for mce_mlp_forward; its mu and
+   * sigma are used) and its bfloat16 copy from mce_mlp_to_bf16.  Both are
+   * read only; NULL for every other schedule. */
+  const float* sched_model;
+  const uint16_t* sched_model_bf16;
 } mce_opts;
 
 typedef struct {
@@ -187,6 +205,9 @@ typedef struct {
   uint64_t* hash;
   uint64_t* size_hist;
   uint64_t hist_len;
+  /* MCE_SCHED_MLP: the predicted cost of every vertex's subproblem (device
+   * array of n floats, the values that ordered the queue); NULL = not wanted */
+  float* sched_cost;
 } mce_per_vertex;
 
 /* All maximal cliques of `g` (Algorithm 4 over Algorithm 1).

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmce.so")
 
 MCE_OK, MCE_EINVAL, MCE_ENOMEM, MCE_ENOSPC, MCE_EDEVICE, MCE_ENOTSUP, MCE_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 RANKS = {"degree": 0, "degeneracy": 1, "triangle": 2, "ttt_root": 3, "peel": 4}
-SCHEDS = {"degree": 0, "triangle": 1, "cost": 2, "id": 3}
+SCHEDS = {"degree": 0, "triangle": 1, "cost": 2, "id": 3, "mlp": 4}
 
 
 class MceError(RuntimeError):
@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
                 ("sched_cost", ctypes.c_void_p), ("waves_per_cu", ctypes.c_uint32),
                 ("donate_interval", ctypes.c_uint32), ("frame_cap", ctypes.c_uint32), ("split", ctypes.c_uint32),
                 ("compact_waves_per_cu", ctypes.c_uint32), ("inline_compact", ctypes.c_uint32),
-                ("compact_order", ctypes.c_uint32), ("lds_row_words", ctypes.c_uint32)]
+                ("compact_order", ctypes.c_uint32), ("lds_row_words", ctypes.c_uint32), ("hand_mb", ctypes.c_uint32),
+                ("sched_model", ctypes.c_void_p), ("sched_model_bf16", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):
@@ -61,7 +62,7 @@ class _CliqueBuf(ctypes.Structure):
 
 class _PerVertex(ctypes.Structure):
     _fields_ = [("nodes", ctypes.c_void_p), ("count", ctypes.c_void_p), ("hash", ctypes.c_void_p),
-                ("size_hist", ctypes.c_void_p), ("hist_len", ctypes.c_uint64)]
+                ("size_hist", ctypes.c_void_p), ("hist_len", ctypes.c_uint64), ("sched_cost", ctypes.c_void_p)]
 
 
 class _ImceResult(ctypes.Structure):
@@ -182,7 +183,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0, donate_interval=0,
           frame_cap=0, split=0, compact_waves_per_cu=0, inline_compact=False, compact_order=0,
-          lds_row_words=0) -> _Opts:
+          lds_row_words=0, model=None, hand_mb=0) -> _Opts:
     o = _Opts()
     o.sched = SCHEDS[sched]
     o.validate = int(bool(validate))
@@ -196,6 +197,12 @@ def _opts(sched="degree", validate=False, stream=None, cost=None, waves_per_cu=0
     o.inline_compact = int(bool(inline_compact))
     o.compact_order = int(compact_order)
     o.lds_row_words = int(lds_row_words)
+    o.hand_mb = int(hand_mb)
+    if sched == "mlp":
+        if model is None:
+            raise ValueError("sched='mlp' needs model= (a costmodel.CostModel)")
+        o.sched_model = model.params.data_ptr()
+        o.sched_model_bf16 = model.bf16().data_ptr()
     return o
 
 
@@ -208,7 +215,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
                frame_cap: int = 0, cap_cliques: int = 1 << 16, cap_verts: int = 1 << 20,
                split: int = 0, compact_waves_per_cu: int = 0, inline_compact: bool = False,
                compact_order: int = 0, size_hist: int = 0, noalloc: bool = False,
-               lds_row_words: int = 0) -> Dict[str, object]:
+               lds_row_words: int = 0, model=None, sched_cost_out: bool = False,
+               hand_mb: int = 0) -> Dict[str, object]:
     """All maximal cliques of `g` (a graphgen.Graph or DeviceGraph).
 
     Returns a dict with count, set_hash, nodes_total, donated, subproblems,
@@ -218,12 +226,15 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
     noalloc=True the call goes to mce_static_noalloc (no device allocation
     inside the library; the outputs are allocated here, by torch); with
     size_hist=L > 1 also 'size_hist', a numpy uint64 array of L entries (entry
-    k = maximal cliques with k vertices, the last entry L-1 or more)."""
+    k = maximal cliques with k vertices, the last entry L-1 or more).
+    sched='mlp' evaluates the cost model `model` (costmodel.CostModel) inside
+    the call to order the queue; sched_cost_out=True returns its predictions
+    as 'sched_cost' (float32 device tensor)."""
     torch = _torch()
     dg = _as_device_graph(g)
     csr = dg.csr()
     o = _opts(sched, validate, stream, cost, waves_per_cu, donate_interval, frame_cap, split, compact_waves_per_cu,
-              inline_compact, compact_order, lds_row_words)
+              inline_compact, compact_order, lds_row_words, model, hand_mb)
     entry = lib().mce_static_noalloc if noalloc else lib().mce_static
     res = _Result()
     pv = None
@@ -234,11 +245,15 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
             tensors[k] = torch.zeros(max(dg.n, 1), dtype=torch.int64, device=dg.row_ptr.device)
     if size_hist:
         hist = torch.zeros(int(size_hist), dtype=torch.int64, device=dg.row_ptr.device)
-    if per_vertex or size_hist:
+    costs = None
+    if sched_cost_out:
+        costs = torch.zeros(max(dg.n, 1), dtype=torch.float32, device=dg.row_ptr.device)
+    if per_vertex or size_hist or sched_cost_out:
         pv = _PerVertex(tensors["nodes_v"].data_ptr() if per_vertex else None,
                         tensors["count_v"].data_ptr() if per_vertex else None,
                         tensors["hash_v"].data_ptr() if per_vertex else None,
-                        hist.data_ptr() if hist is not None else None, int(size_hist))
+                        hist.data_ptr() if hist is not None else None, int(size_hist),
+                        costs.data_ptr() if costs is not None else None)
     out = {}
     if cliques:
         cc, cv = cap_cliques, cap_verts
@@ -269,6 +284,8 @@ def mce_static(g, rank: str = "degree", sched: str = "degree", cliques: bool = F
             out[k] = t[:dg.n]
     if hist is not None:
         out["size_hist"] = hist.cpu().numpy().view(np.uint64)
+    if costs is not None:
+        out["sched_cost"] = costs[:dg.n]
     return out
 
 

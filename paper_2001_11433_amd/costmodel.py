@@ -63,8 +63,18 @@ class CostModel:
         self.loss_buf = torch.zeros(1, dtype=torch.float32, device=device)
         self.p16 = torch.zeros(self.params.numel(), dtype=torch.int16, device=device)
         self.step = 0
+        self._p16_step = None  # the training step p16 was rounded at
+
+    def bf16(self):
+        """The bfloat16 parameter block (rounded again only after training steps)."""
+        key = (self.step, self.params.data_ptr())
+        if self._p16_step != key:
+            _check(lib().mce_mlp_to_bf16(self.params.data_ptr(), self.p16.data_ptr(), _stream_ptr(None)))
+            self._p16_step = key
+        return self.p16
 
     def fit_norm(self, feat):
+        self._p16_step = None
         _check(lib().mce_mlp_fit_norm(self.params.data_ptr(), feat.data_ptr(), int(feat.shape[0]),
                                       _stream_ptr(None)))
 
@@ -92,8 +102,7 @@ class CostModel:
         n = int(feat.shape[0])
         out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
         if bf16:
-            _check(lib().mce_mlp_to_bf16(self.params.data_ptr(), self.p16.data_ptr(), _stream_ptr(None)))
-            _check(lib().mce_mlp_forward_bf16(self.p16.data_ptr(), self.params.data_ptr(), feat.data_ptr(), n,
+            _check(lib().mce_mlp_forward_bf16(self.bf16().data_ptr(), self.params.data_ptr(), feat.data_ptr(), n,
                                               out.data_ptr(), _stream_ptr(None)))
         else:
             _check(lib().mce_mlp_forward(self.params.data_ptr(), feat.data_ptr(), n, out.data_ptr(),

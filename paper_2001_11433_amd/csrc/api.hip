@@ -78,8 +78,18 @@ namespace {
 // calls on the same device, guarded by one mutex per device.
 struct Workspace {
   DevBuf rp, col, metric, tri, core, coredeg, corelist, corectl, P, X, xmark, lidx, words, gwords, off, goff, stats, arena,
-      gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad, split, split_total;
+      gids, keys, vals, keys2, vals2, iota, clq_off, clq_vert, bad, split, split_total, feat, cost;
   EnumWork ew;
+  // second stream of the learned schedule (features and inference while the
+  // subproblems are built), created on first use; default priority
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int side_init() {
+    if (!side) MCE_TRY_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (!ev_fork) MCE_TRY_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    if (!ev_join) MCE_TRY_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    return MCE_OK;
+  }
   void* scan_tmp = nullptr;
   size_t scan_bytes = 0;
   void* sort_tmp = nullptr;
@@ -256,6 +266,13 @@ int compute_metric(mce_rank rank, uint64_t n, const uint64_t* rp, const uint32_t
 // run, at most kHandRecsMax records in kHandUnitsMax 64-byte units (64 GiB).
 constexpr uint64_t kHandRecsMax = 1ULL << 26;
 constexpr uint64_t kHandUnitsMax = 1ULL << 30;
+constexpr uint64_t kHandDefaultMb = 16384;
+
+// The arena's budget in 64-byte units (mce_opts.hand_mb).
+uint64_t hand_budget_units(const mce_opts& o) {
+  const uint64_t mb = o.hand_mb ? o.hand_mb : kHandDefaultMb;
+  return std::min<uint64_t>(mb << 14, kHandUnitsMax);
+}
 constexpr uint32_t kCompactWavesPerCu = 20;
 
 uint32_t enum_grid(const mce_opts& opts) {
@@ -328,7 +345,7 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
       // sized to what the previous run asked for; requests beyond the
       // capacity are searched in place
       const uint64_t first = std::max<uint64_t>(j.hand_initial_units, 1u << 20);
-      const uint64_t units = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_units, first), kHandUnitsMax);
+      const uint64_t units = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_units, first), hand_budget_units(opts));
       // a record takes at least one unit
       hand_cap = std::min<uint64_t>(std::max<uint64_t>(w.hand_want_recs, units), kHandRecsMax);
       MCE_TRY(w.hand.ensure(units * 64));
@@ -419,8 +436,12 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     set_error("MCE_SCHED_COST needs sched_cost");
     return MCE_EINVAL;
   }
-  if ((unsigned)opts.sched > MCE_SCHED_ID) {
+  if ((unsigned)opts.sched > MCE_SCHED_MLP) {
     set_error("unknown schedule %d", (int)opts.sched);
+    return MCE_EINVAL;
+  }
+  if (opts.sched == MCE_SCHED_MLP && (!opts.sched_model || !opts.sched_model_bf16)) {
+    set_error("MCE_SCHED_MLP needs sched_model and sched_model_bf16");
     return MCE_EINVAL;
   }
   if (cl && ((cl->cap_cliques && !cl->off) || (cl->cap_verts && !cl->vert))) {
@@ -468,6 +489,48 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
     }
   }
   MCE_TRY_HIP(tm.record(1, s));
+
+  // --- learned schedule: the cost model's inputs and prediction on a second
+  // stream, forked here and joined before the queue is ordered, so they
+  // overlap the subproblem build (the allocation-free call creates no streams
+  // or events and runs them in order on s)
+  const bool mlp = opts.sched == MCE_SCHED_MLP;
+  float* mlp_cost = nullptr;
+  hipStream_t side = s;
+  const uint64_t* mlp_tri = nullptr;
+  if (mlp) {
+    MCE_TRY(ws.feat.ensure(n * 4 * sizeof(float)));
+    if (pv && pv->sched_cost) {
+      mlp_cost = pv->sched_cost;
+    } else {
+      MCE_TRY(ws.cost.ensure(n * sizeof(float)));
+      mlp_cost = ws.cost.as<float>();
+    }
+    if (rank != MCE_RANK_TRIANGLE && !tri) {
+      MCE_TRY(ws.tri.ensure(n * sizeof(uint64_t)));
+    }
+    if (rank != MCE_RANK_DEGENERACY) {
+      // every buffer of the side work is sized before the fork
+      MCE_TRY(ws.core.ensure(n * sizeof(uint64_t)));
+      MCE_TRY(ws.coredeg.ensure(n * sizeof(uint32_t)));
+      MCE_TRY(ws.corelist.ensure(n * sizeof(uint32_t)));
+      MCE_TRY(ws.corectl.ensure(8 * sizeof(uint64_t)));
+    }
+    if (!noalloc) {
+      MCE_TRY(ws.side_init());
+      side = ws.side;
+      MCE_TRY_HIP(hipEventRecord(ws.ev_fork, s));
+      MCE_TRY_HIP(hipStreamWaitEvent(side, ws.ev_fork, 0));
+    }
+    if (rank == MCE_RANK_TRIANGLE) {
+      mlp_tri = metric;
+    } else if (tri) {
+      mlp_tri = tri;
+    } else {
+      MCE_TRY_HIP(launch_triangles(n, rp, col, ws.tri.as<uint64_t>(), side));
+      mlp_tri = ws.tri.as<uint64_t>();
+    }
+  }
 
   // --- subproblem sizes and build (Algorithm 4, body)
   MCE_TRY(ws.P.ensure(n * sizeof(uint32_t)));
@@ -526,12 +589,33 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   MCE_TRY_HIP(launch_build(n, rp, col, metric, b, ws.off.as<uint64_t>(), ws.goff.as<uint64_t>(),
                            ws.arena.as<uint64_t>(), ws.gids.as<uint32_t>(), s));
 
+  if (mlp) {
+    // core numbers (the rank's own metric under degeneracy ownership; the
+    // peeling waits on the host between rounds, which is why it is enqueued
+    // after the build), features, then the BF16 forward
+    const uint64_t* core = metric;
+    if (rank != MCE_RANK_DEGENERACY) {
+      MCE_TRY(run_core_numbers(n, rp, col, ws.core.as<uint64_t>(), ws.coredeg.as<uint32_t>(),
+                               ws.corelist.as<uint32_t>(), ws.corectl.as<uint64_t>(), side));
+      core = ws.core.as<uint64_t>();
+    }
+    MCE_TRY_HIP(launch_features(n, rp, col, core, mlp_tri, ws.feat.as<float>(), side));
+    MCE_TRY_HIP(launch_mlp_forward_bf16(opts.sched_model, opts.sched_model_bf16, ws.feat.as<float>(), n, mlp_cost,
+                                        side));
+    if (side != s) {
+      MCE_TRY_HIP(hipEventRecord(ws.ev_join, side));
+      MCE_TRY_HIP(hipStreamWaitEvent(s, ws.ev_join, 0));
+    }
+  }
+  const mce_sched qsched = mlp ? MCE_SCHED_COST : opts.sched;
+  const float* qcost = mlp ? mlp_cost : opts.sched_cost;
+
   // --- queue order (never changes results)
   MCE_TRY(ws.keys.ensure(n * sizeof(uint64_t)));
   MCE_TRY(ws.keys2.ensure(n * sizeof(uint64_t)));
   MCE_TRY(ws.vals.ensure(n * sizeof(uint32_t)));
   MCE_TRY(ws.vals2.ensure(n * sizeof(uint32_t)));
-  MCE_TRY_HIP(launch_queue_keys(n, rp, b.p, opts.sched, tri, opts.sched_cost, ws.keys.as<uint64_t>(),
+  MCE_TRY_HIP(launch_queue_keys(n, rp, b.p, qsched, tri, qcost, ws.keys.as<uint64_t>(),
                                 ws.vals.as<uint32_t>(), nullptr, s));
   uint64_t* skeys;
   uint32_t* svals;
@@ -541,10 +625,10 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ws.iota.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
   const uint32_t* split = nullptr;
-  if (opts.sched == MCE_SCHED_COST && opts.split > 1) {
+  if (qsched == MCE_SCHED_COST && opts.split > 1) {
     MCE_TRY(ws.split.ensure(n * sizeof(uint32_t)));
     MCE_TRY(ws.split_total.ensure(sizeof(double)));
-    MCE_TRY_HIP(launch_split_plan(n, b.p, opts.sched_cost, enum_grid(opts), std::min<uint32_t>(opts.split, 0xFFFFu),
+    MCE_TRY_HIP(launch_split_plan(n, b.p, qcost, enum_grid(opts), std::min<uint32_t>(opts.split, 0xFFFFu),
                                   ws.split_total.as<double>(), ws.split.as<uint32_t>(), s));
     split = ws.split.as<uint32_t>();
   }

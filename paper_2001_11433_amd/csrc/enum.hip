@@ -32,6 +32,8 @@
 #include "dev.h"
 #include "internal.h"
 
+#include <type_traits>
+
 namespace mce {
 
 namespace {
@@ -45,12 +47,31 @@ enum { R_S = 0, R_TYPE = 1, R_DEPTH = 2, R_KLEN = 3, R_HDR = 4 };
 // compact record: a frame (kCF words) at R_HDR, then rows and tables
 constexpr uint32_t kCR_PP = 12, kCR_XP = 76, kCR_PX = 140, kCR_EX = 204, kCR_KEY = 268, kCR_GP = 332, kCR_K = 364;
 
+// Per-wave diagnostic counters (see mce_result.diag).
+struct Diag {
+  uint64_t rebases, cnodes, t_rebase, t_compact, t_idle, t_donate, attempts, tasks;
+};
+
+// Per-wave totals and diagnostics.  They change only at task boundaries and
+// on donation attempts, so they live in the wave's LDS (lane 0 updates them)
+// instead of holding 28 scalar registers for the whole kernel, registers the
+// search loop needs.  Intervals are tallied as -start ... +end.
+struct WaveStat {
+  uint64_t c, h, n, ops, xops, lds;
+  Diag dg;
+};
+
+__device__ __forceinline__ void stat_add(uint64_t& f, uint64_t v) {
+  if (lane_id() == 0) f += v;
+}
+
 struct Lds {
   uint64_t sP[64];
   uint64_t cstk[kCFrames * kCF];
   uint32_t kG[kKLds];  // ids of K, roots first
   uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
   uint64_t hist[kHistLds];  // clique sizes tallied by this wave (when requested)
+  WaveStat st;
 };
 
 // LDS of the compact kernel: frames and a K list long enough for a handed-off
@@ -59,6 +80,7 @@ struct LdsC {
   uint64_t cstk[kCFrames * kCF];
   uint32_t kG[kHandK + kCFrames + 2];
   uint64_t hist[kHistLds];
+  WaveStat st;
 };
 
 static_assert(kHistLds == kWave, "one LDS histogram bin per lane");
@@ -100,11 +122,6 @@ struct Acc {
   }
   // algorithmic LDS bytes of the formula 4 * w * (s + |ext|)
   __device__ uint64_t lds_bytes(uint32_t wv) const { return 4ULL * wv * (ssum + esum); }
-};
-
-// Per-wave diagnostic counters (see mce_result.diag).
-struct Diag {
-  uint64_t rebases, cnodes, t_rebase, t_compact, t_idle, t_donate, attempts, tasks;
 };
 
 __device__ __forceinline__ uint64_t now() { return __builtin_readcyclecounter(); }
@@ -492,7 +509,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
   uint32_t d = 0;       // frames on the stack (each with deep children left)
   uint32_t kl = kbase;  // |K| of the current node
   bool framed = false;  // the current node's frame is the top of the stack
-  const uint64_t t0 = now();
+  stat_add(dg.t_compact, 0 - now());
   const uint32_t dlim = 4 * a.donate_interval;
   const uint64_t lower = (1ULL << lane) - 1;  // the children before this lane's
   VTally T;
@@ -636,10 +653,10 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
 
     if (can_donate && ++since >= dlim) {
       since = 0;
-      const uint64_t td = now();
+      stat_add(dg.t_donate, 0 - now());
       for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
-        ++dg.attempts;
-        if constexpr (sizeof(LT) == sizeof(Lds)) {
+        stat_add(dg.attempts, 1);
+        if constexpr (std::is_same<LT, Lds>::value) {
           if (wide && donate_wide(a, L, *wide, can_donate)) continue;
         }
         // the shallowest frame with two or more deep children left gives away
@@ -678,12 +695,12 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         if (lane == 0) L.cstk[i * kCF + 7] = km;
         publish_record(a, blk);
       }
-      dg.t_donate += now() - td;
+      stat_add(dg.t_donate, now());
     }
   }
-  dg.cnodes += T.tn;
+  stat_add(dg.cnodes, T.tn);
   T.flush(acc);
-  dg.t_compact += now() - t0;
+  stat_add(dg.t_compact, now());
 }
 
 // Tie-break keys: rank of each compact row's vertex id among all compact rows
@@ -746,18 +763,83 @@ __device__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* k
 //   rowPP[np], rowXP[nx], rowPX[np], (rowEx[np] with exclusion) as u64
 //   gP[np], gX[nx], K[klen] as u32
 // The tie-break keys are recomputed from gP and gX on the other side.
-__device__ __forceinline__ uint32_t hand_words(uint32_t np, uint32_t nx, uint32_t klen, bool excl) {
-  return 4 + 2 * np + nx + (excl ? np : 0) + (np + nx + klen + 1) / 2;
+__device__ __forceinline__ uint32_t hand_words(uint32_t wp, uint32_t nx, uint32_t klen, bool excl) {
+  return 4 + (excl ? 2 : 1) * wp + (nx + klen + 1) / 2;
 }
 
-// Reserves and writes one record; false when the arena or the index is full
-// (the request still counts, so the host learns the size it needs).
+// Re-bases a wide node onto the compact 64 + 64 universe: gathers the rows of
+// its candidates (the set bits of the wide mask rP, lane k holding word k, in
+// ascending order) and of its kept fini vertices (local row ux, lane < nx)
+// from the subproblem's bit rows.  Sets c (rows, ids, np, nx), the fini ids
+// gX (lane < nx) and, with exclusion, the compact mask of candidates whose
+// branch is excluded (from the wide mask rF, lane k holding word k).
 template <bool EXCL>
-__device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, const Compact& c, uint32_t gX, uint32_t s, uint64_t F,
-                         uint64_t zsum, uint32_t klen) {
+__device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const uint32_t* gid, uint64_t nrow,
+                               uint32_t wp, uint64_t rP, uint64_t rF, uint32_t ux, uint32_t np, uint32_t nx,
+                               Compact& c, uint32_t& gX, uint64_t& Fc) {
   const int lane = lane_id();
-  const uint32_t np = c.np, nx = c.nx;
-  const uint32_t units = (hand_words(np, nx, klen, EXCL) + 7) / 8;
+  c.np = np;
+  c.nx = nx;
+  uint32_t pm = 0;  // lane j: local row of the j-th candidate
+  {
+    uint32_t j = 0;
+    for (uint32_t k = 0; k < wp; ++k) {
+      uint64_t m = readlane64(rP, k);
+      while (m) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(m);
+        if (lane == (int)j) pm = k * 64 + b;
+        ++j;
+        m &= m - 1;
+      }
+    }
+  }
+  uint64_t cPP = 0, cXP = 0, cEx = 0, cF = 0;
+  uint32_t cnt = 0;
+  for (uint32_t k = 0; k < wp; ++k) {
+    uint64_t m = readlane64(rP, k);
+    if (m == 0) continue;
+    const uint64_t wP = lane < (int)np ? rowP[(uint64_t)k * nrow + pm] : 0;
+    const uint64_t wX = lane < (int)nx ? rowP[(uint64_t)k * nrow + ux] : 0;
+    const uint64_t wE = (EXCL && lane < (int)np) ? excl[(uint64_t)pm * wp + k] : 0;
+    const uint64_t fk = EXCL ? readlane64(rF, k) : 0;
+    while (m) {
+      const uint32_t b = (uint32_t)__builtin_ctzll(m);
+      cPP |= ((wP >> b) & 1ULL) << cnt;
+      cXP |= ((wX >> b) & 1ULL) << cnt;
+      if (EXCL) {
+        cEx |= ((wE >> b) & 1ULL) << cnt;
+        cF |= ((fk >> b) & 1ULL) << cnt;
+      }
+      ++cnt;
+      m &= m - 1;
+    }
+  }
+  c.rowPP = cPP;
+  c.rowXP = cXP;
+  c.rowEx = cEx;
+  // cand rows over the compact fini columns = transpose of cXP
+  uint64_t cPX = 0;
+  for (uint32_t j = 0; j < np; ++j) {
+    const uint64_t col = ballot(lane < (int)nx && ((cXP >> j) & 1ULL));
+    if (lane == (int)j) cPX = col;
+  }
+  c.rowPX = cPX;
+  c.gP = lane < (int)np ? gid[pm] : 0xFFFFFFFFu;
+  gX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
+  Fc = EXCL ? readlane64(cF, 0) : 0;
+}
+
+// Hands a re-based node to the compact kernel: one record of its subproblem,
+// K, zsum, the wide masks of its candidates (and excluded branches) and the
+// local rows of its kept fini vertices; the compact kernel gathers the rows
+// itself (compact_gather), so a record holds no row data.  False when the
+// arena or the index is full (the request still counts, so the host learns
+// the size it needs).
+template <bool EXCL>
+__device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint32_t wp, uint64_t rP, uint64_t rF,
+                         uint32_t ux, uint32_t np, uint32_t nx, uint64_t zsum, uint32_t klen) {
+  const int lane = lane_id();
+  const uint32_t units = (hand_words(wp, nx, klen, EXCL) + 7) / 8;
   uint64_t old = 0;
   if (lane == 0) old = fetch_add(&a.ctl[CTL_HAND], (1ULL << 32) | units);
   old = readlane64(old, 0);
@@ -769,56 +851,54 @@ __device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, const Compact& c
     rec[0] = (uint64_t)s | ((uint64_t)np << 32) | ((uint64_t)nx << 40);
     rec[1] = klen;
     rec[2] = zsum;
-    rec[3] = F;
+    rec[3] = 0;
     a.hand_idx[idx] = (uint32_t)at;
     fetch_add(&a.ctl[CTL_HANDOK], 1);
   }
   uint64_t* w = rec + 4;
-  if (lane < (int)np) w[lane] = c.rowPP;
-  w += np;
-  if (lane < (int)nx) w[lane] = c.rowXP;
-  w += nx;
-  if (lane < (int)np) w[lane] = c.rowPX;
-  w += np;
+  if (lane < (int)wp) w[lane] = rP;
+  w += wp;
   if (EXCL) {
-    if (lane < (int)np) w[lane] = c.rowEx;
-    w += np;
+    if (lane < (int)wp) w[lane] = rF;
+    w += wp;
   }
   uint32_t* u = (uint32_t*)w;
-  if (lane < (int)np) u[lane] = c.gP;
-  if (lane < (int)nx) u[np + lane] = gX;
-  for (uint32_t j = lane; j < klen; j += kWave) u[np + nx + j] = kG[j];
+  if (lane < (int)nx) u[lane] = ux;
+  for (uint32_t j = lane; j < klen; j += kWave) u[nx + j] = kG[j];
   return true;
 }
 
 // Reads a handoff record into compact form (the node still to be expanded).
 template <bool EXCL, class LT>
-__device__ void compact_from_hand(const uint64_t* rec, Compact& c, LT& L, uint64_t& P, uint64_t& Xx, uint64_t& zsum,
-                                  uint64_t& F, uint32_t& klen) {
+__device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compact& c, LT& L, uint64_t& P,
+                                  uint64_t& Xx, uint64_t& zsum, uint64_t& F, uint32_t& klen, uint32_t& s) {
   const int lane = lane_id();
   const uint64_t h = readlane64(rec[0], 0);
-  c.np = (uint32_t)(h >> 32) & 0xFF;
-  c.nx = (uint32_t)(h >> 40) & 0xFF;
+  s = (uint32_t)h;
+  const uint32_t np = (uint32_t)(h >> 32) & 0xFF, nx = (uint32_t)(h >> 40) & 0xFF;
   klen = (uint32_t)readlane64(rec[1], 0);
   zsum = readlane64(rec[2], 0);
-  F = readlane64(rec[3], 0);
-  const uint32_t np = c.np, nx = c.nx;
+  const uint32_t p = readlane32(a.sub.p[s], 0);
+  const uint32_t x = readlane32(a.sub.x[s], 0);
+  const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6;
+  const uint64_t nrow = (uint64_t)p + x;
+  const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
+  const uint64_t* excl = rowG + (uint64_t)wp * nrow + (uint64_t)p * wx;
+  const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
   const uint64_t* w = rec + 4;
-  c.rowPP = lane < (int)np ? w[lane] : 0;
-  w += np;
-  c.rowXP = lane < (int)nx ? w[lane] : 0;
-  w += nx;
-  c.rowPX = lane < (int)np ? w[lane] : 0;
-  w += np;
-  c.rowEx = 0;
+  const uint64_t rP = lane < (int)wp ? w[lane] : 0;
+  w += wp;
+  uint64_t rF = 0;
   if (EXCL) {
-    c.rowEx = lane < (int)np ? w[lane] : 0;
-    w += np;
+    rF = lane < (int)wp ? w[lane] : 0;
+    w += wp;
   }
   const uint32_t* u = (const uint32_t*)w;
-  c.gP = lane < (int)np ? u[lane] : 0xFFFFFFFFu;
-  c.keyX = lane < (int)nx ? u[np + lane] : 0xFFFFFFFFu;
-  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[np + nx + j];
+  const uint32_t ux = lane < (int)nx ? u[lane] : 0;
+  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[nx + j];
+  uint32_t gX;
+  compact_gather<EXCL>(rowG, excl, gid, nrow, wp, rP, rF, ux, np, nx, c, gX, F);
+  c.keyX = gX;
   compact_keys(c);
   P = np == 64 ? ~0ULL : ((1ULL << np) - 1);
   Xx = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
@@ -833,10 +913,10 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
   const int lane = threadIdx.x;
   uint64_t* const gstk = a.stacks + (uint64_t)blockIdx.x * a.stack_words;
   uint32_t* const gK = a.kbig ? a.kbig + (uint64_t)blockIdx.x * kKBig : nullptr;
-  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0, tot_xops = 0, tot_lds = 0;
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
-  Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (lane == 0) L.st = WaveStat{};
+  Diag& dg = L.st.dg;
   const uint64_t t_start = now();
   hist_clear(a, L.hist);
 
@@ -845,9 +925,9 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
     const uint64_t tw = now();
     if (lane == 0) ref = claim_task(a);
     ref = readlane64(ref, 0);
-    dg.t_idle += now() - tw;
+    stat_add(dg.t_idle, now() - tw);
     if (ref == 0) break;
-    ++dg.tasks;
+    stat_add(dg.tasks, 1);
 
     const bool cont = (ref >> 63) != 0;
     const uint32_t blk = cont ? (uint32_t)(ref & 0xFFFFFFFFULL) : kNil;
@@ -1031,74 +1111,30 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
             }
             bool rebased = false;
             if (ok) {
-                // re-base this node and search its subtree in compact form
+                // re-base this node and search its subtree in compact form,
+                // here or (handed off) in the compact kernel
                 const uint64_t tr = now();
-                ++dg.rebases;
-                Compact c;
-                c.np = p_cnt;
-                c.nx = nx;
-                uint32_t pm = 0;
-                {
-                  uint32_t j = 0;
-                  for (uint32_t k = 0; k < wp; ++k) {
-                    uint64_t m = readlane64(rP, k);
-                    while (m) {
-                      const uint32_t b = (uint32_t)__builtin_ctzll(m);
-                      if (lane == (int)j) pm = k * 64 + b;
-                      ++j;
-                      m &= m - 1;
-                    }
-                  }
-                }
+                stat_add(dg.rebases, 1);
                 __syncthreads();
                 const uint32_t ux = lane < (int)nx ? L.xl[lane] : 0;
-                uint64_t cPP = 0, cXP = 0, cEx = 0, cF = 0;
-                uint32_t cnt = 0;
-                for (uint32_t k = 0; k < wp; ++k) {
-                  uint64_t m = readlane64(rP, k);
-                  if (m == 0) continue;
-                  const uint64_t wP = lane < (int)c.np ? rowP[(uint64_t)k * nrow + pm] : 0;
-                  const uint64_t wX = lane < (int)nx ? rowP[(uint64_t)k * nrow + ux] : 0;
-                  const uint64_t wE = (EXCL && lane < (int)c.np) ? excl[(uint64_t)pm * wp + k] : 0;
-                  const uint64_t fk = EXCL ? readlane64(rF, k) : 0;
-                  while (m) {
-                    const uint32_t b = (uint32_t)__builtin_ctzll(m);
-                    cPP |= ((wP >> b) & 1ULL) << cnt;
-                    cXP |= ((wX >> b) & 1ULL) << cnt;
-                    if (EXCL) {
-                      cEx |= ((wE >> b) & 1ULL) << cnt;
-                      cF |= ((fk >> b) & 1ULL) << cnt;
-                    }
-                    ++cnt;
-                    m &= m - 1;
-                  }
-                }
-                c.rowPP = cPP;
-                c.rowXP = cXP;
-                c.rowEx = cEx;
-                // cand rows over the compact fini columns = transpose of cXP
-                uint64_t cPX = 0;
-                for (uint32_t j = 0; j < c.np; ++j) {
-                  const uint64_t col = ballot(lane < (int)nx && ((cXP >> j) & 1ULL));
-                  if (lane == (int)j) cPX = col;
-                }
-                c.rowPX = cPX;
-                c.gP = lane < (int)c.np ? gid[pm] : 0xFFFFFFFFu;
-                const uint32_t gX = lane < (int)nx ? gid[ux] : 0xFFFFFFFFu;
-                const uint64_t Fc = EXCL ? readlane64(cF, 0) : 0;
                 wctx.top = d;
-                const bool handed = a.hand && kroot + d <= kHandK && hand_off<EXCL>(a, kG, c, gX, s, Fc, zsum, kroot + d);
+                const bool handed = a.hand && kroot + d <= kHandK &&
+                                    hand_off<EXCL>(a, kG, s, wp, rP, rF, ux, p_cnt, nx, zsum, kroot + d);
                 if (handed) {
                   // a handed-off subtree is work done here as far as donation
                   // pacing goes, else the wide frames would rarely be offered
                   since += a.donate_interval / 16 + 1;
-                  dg.t_rebase += now() - tr;
+                  stat_add(dg.t_rebase, now() - tr);
                 } else {
+                  Compact c;
+                  uint32_t gX;
+                  uint64_t Fc;
+                  compact_gather<EXCL>(rowP, excl, gid, nrow, wp, rP, rF, ux, p_cnt, nx, c, gX, Fc);
                   c.keyX = gX;
                   compact_keys(c);
                   const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
                   const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
-                  dg.t_rebase += now() - tr;
+                  stat_add(dg.t_rebase, now() - tr);
                   if (bigk)
                     compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, acc,
                                             can_donate, since, &wctx, dg);
@@ -1179,13 +1215,13 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
             // hand the second half of the shallowest unvisited siblings to idle waves
             if (can_donate && ++since >= a.donate_interval) {
               since = 0;
-              const uint64_t td = now();
+              stat_add(dg.t_donate, 0 - now());
               wctx.top = d;
               if (starving(a)) {
-                ++dg.attempts;
+                stat_add(dg.attempts, 1);
                 donate_wide(a, L, wctx, can_donate);
               }
-              dg.t_donate += now() - td;
+              stat_add(dg.t_donate, now());
             }
             continue;
           }
@@ -1213,21 +1249,24 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
       if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
       fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
     }
-    tot_n += acc.tn;
-    tot_c += acc.tc;
-    tot_h += acc.th;
-    tot_ops += acc.ops(wv);
-    tot_xops += acc.exec_ops((p + 63) >> 6);
-    tot_lds += acc.lds_bytes(wv);
+    if (lane == 0) {
+      L.st.n += acc.tn;
+      L.st.c += acc.tc;
+      L.st.h += acc.th;
+      L.st.ops += acc.ops(wv);
+      L.st.xops += acc.exec_ops((p + 63) >> 6);
+      L.st.lds += acc.lds_bytes(wv);
+    }
   }
   hist_flush(a, L.hist);
   if (lane == 0) {
-    if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
-    if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
-    if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
-    if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
-    if (tot_xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)tot_xops);
-    if (tot_lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)tot_lds);
+    const WaveStat& t = L.st;
+    if (t.c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)t.c);
+    if (t.h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)t.h);
+    if (t.n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)t.n);
+    if (t.ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)t.ops);
+    if (t.xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)t.xops);
+    if (t.lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)t.lds);
     const uint64_t t_all = now() - t_start;
     // donation inside the compact path is also inside t_compact
     const uint64_t t_wide = t_all - dg.t_idle - dg.t_rebase - dg.t_compact;
@@ -1250,19 +1289,19 @@ template <bool EXCL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_compact(EnumArgs a) {
   __shared__ LdsC L;
   const int lane = threadIdx.x;
-  uint64_t tot_c = 0, tot_h = 0, tot_n = 0, tot_ops = 0, tot_xops = 0, tot_lds = 0;
   bool can_donate = a.max_tickets > 0;
   uint32_t since = 0;
-  Diag dg = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (lane == 0) L.st = WaveStat{};
+  Diag& dg = L.st.dg;
   hist_clear(a, L.hist);
   for (;;) {
     uint64_t ref = 0;
     const uint64_t tw = now();
     if (lane == 0) ref = claim_task(a);
     ref = readlane64(ref, 0);
-    dg.t_idle += now() - tw;
+    stat_add(dg.t_idle, now() - tw);
     if (ref == 0) break;
-    ++dg.tasks;
+    stat_add(dg.tasks, 1);
     const bool pooled = (ref >> 63) != 0;
     const uint64_t idx = ref & 0xFFFFFFFFULL;
     Acc acc = {0, 0, 0, 0, 0, 0, 0};
@@ -1278,8 +1317,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
       if (lane == 0) pool_push(a, (uint32_t)idx);
     } else {
       const uint64_t* rec = a.hand + (uint64_t)a.hand_idx[idx] * 8;
-      s = (uint32_t)readlane64(rec[0], 0);
-      compact_from_hand<EXCL>(rec, c, L, P, Xx, zsum, F, klen);
+      compact_from_hand<EXCL>(a, rec, c, L, P, Xx, zsum, F, klen, s);
     }
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
@@ -1292,21 +1330,24 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
       if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
       fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
     }
-    tot_n += acc.tn;
-    tot_c += acc.tc;
-    tot_h += acc.th;
-    tot_ops += acc.ops(wv);
-    tot_xops += acc.exec_ops((p + 63) >> 6);
-    tot_lds += acc.lds_bytes(wv);
+    if (lane == 0) {
+      L.st.n += acc.tn;
+      L.st.c += acc.tc;
+      L.st.h += acc.th;
+      L.st.ops += acc.ops(wv);
+      L.st.xops += acc.exec_ops((p + 63) >> 6);
+      L.st.lds += acc.lds_bytes(wv);
+    }
   }
   hist_flush(a, L.hist);
   if (lane == 0) {
-    if (tot_c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)tot_c);
-    if (tot_h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)tot_h);
-    if (tot_n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)tot_n);
-    if (tot_ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)tot_ops);
-    if (tot_xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)tot_xops);
-    if (tot_lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)tot_lds);
+    const WaveStat& t = L.st;
+    if (t.c) atomicAdd((unsigned long long*)&a.ctl[CTL_COUNT], (unsigned long long)t.c);
+    if (t.h) atomicAdd((unsigned long long*)&a.ctl[CTL_HASH], (unsigned long long)t.h);
+    if (t.n) atomicAdd((unsigned long long*)&a.ctl[CTL_NODES], (unsigned long long)t.n);
+    if (t.ops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS], (unsigned long long)t.ops);
+    if (t.xops) atomicAdd((unsigned long long*)&a.ctl[CTL_OPS_EXEC], (unsigned long long)t.xops);
+    if (t.lds) atomicAdd((unsigned long long*)&a.ctl[CTL_LDS_BYTES], (unsigned long long)t.lds);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 1], (unsigned long long)dg.cnodes);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 4], (unsigned long long)dg.t_compact);
     atomicAdd((unsigned long long*)&a.ctl[CTL_DIAG + 5], (unsigned long long)dg.t_idle);

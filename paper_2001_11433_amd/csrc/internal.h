@@ -265,6 +265,10 @@ hipError_t launch_triangles(uint64_t n, const uint64_t* rp, const uint32_t* col,
 hipError_t launch_features(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* core,
                            const uint64_t* tri, float* feat, hipStream_t s);
 
+// mlp.hip
+hipError_t launch_mlp_forward_bf16(const float* prm, const uint16_t* prm16, const float* feat, uint64_t n, float* out,
+                                   hipStream_t s);
+
 // build.hip
 struct BuildBufs {
   uint32_t* p;       // [n]

@@ -214,6 +214,15 @@ uint32_t grid_for(uint64_t n) {
 }
 
 }  // namespace
+
+// BF16 prediction on stream s without a wait (the static call's schedule).
+hipError_t launch_mlp_forward_bf16(const float* prm, const uint16_t* prm16, const float* feat, uint64_t n, float* out,
+                                   hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_forward<true>, dim3(grid_for(n)), dim3(64), 0, s, prm, prm16, feat, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace mce
 
 using namespace mce;

@@ -2,12 +2,16 @@
 benchmark times (the tuned table).
 
 The oracle cannot enumerate these graphs whole in test time, so:
-  * the 1M-vertex Chung-Lu + communities graph: the per-subproblem triples
-    (search nodes, cliques, clique-set hash) of a seeded sample of vertices,
-    plus the heaviest subproblems, against the oracle's ParMCE on the same
-    vertices; totals against the sums of the per-subproblem triples;
-  * R-MAT scale 18: rank metrics (degree, core number, triangles) of every
-    vertex against the oracle (its enumeration is far beyond reach);
+  * the 1M-vertex Chung-Lu + communities graph: the whole graph against the
+    oracle's full ParMCE stored by oracle/make_golden.py
+    (tests/golden/c3_totals.json: totals, a digest of every per-subproblem
+    triple, the heaviest subproblems, the clique-size distribution); and the
+    per-subproblem triples (search nodes, cliques, clique-set hash) of a seeded
+    sample of vertices against the oracle run in the test;
+  * R-MAT scale 15 (degeneracy ownership): the same sampled per-subproblem
+    check; scale 18: rank metrics (degree, core number, triangles, peel
+    rounds) of every vertex against the oracle (its enumeration is far beyond
+    reach);
   * the 500k-vertex Chung-Lu stream: all eight result fields of all 200
     batches against the oracle's sequential IMCE (stored by
     oracle/make_golden.py in tests/golden/c5_stream.json); sampled new and
@@ -59,6 +63,64 @@ def test_cl1m_communities_sampled_subproblems(m):
     heavy = order[nodes[order] <= 5_000_000][-12:]
     sample = np.unique(np.concatenate([rng.choice(g.n, 384, replace=False), heavy])).astype(np.uint32)
     want = O.mce_parmce(g, "degree", verts=sample, threads=8)
+    assert np.array_equal(nodes[sample], want.nodes_v)
+    assert np.array_equal(count[sample], want.count_v)
+    assert np.array_equal(hsh[sample], want.hash_v)
+
+
+def _digest(*arrays) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype="<u8").tobytes())
+    return h.hexdigest()
+
+
+def test_cl1m_communities_whole_graph_against_the_oracle(m):
+    # every subproblem of the benchmark graph, in the tuned launch, against the
+    # oracle's full ParMCE (tests/golden/c3_totals.json, oracle/make_golden.py):
+    # totals, the per-subproblem triples of all 10^6 vertices (by digest), the
+    # heaviest subproblems one by one, and the clique-size distribution
+    from paper_2001_11433_amd import tuner
+    path = os.path.join(GOLDEN, "c3_totals.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c3_totals.json not written yet (oracle/make_golden.py c3, hours of CPU)")
+    with open(path) as f:
+        want = json.load(f)
+    g = gg.plant_communities(gg.chung_lu(1_000_000, 2.1, 20, seed=0), count=500, smin=30, smax=80, p=0.9, seed=1)
+    assert (g.n, g.m) == (want["n"], want["m"])
+    kw = tuner.launch_kwargs(tuner.lookup(g, "degree", family="cl1m-communities"))
+    got = m.mce_static(g, rank="degree", per_vertex=True, size_hist=4097, **kw)
+    assert got["count"] == want["count"]
+    assert "%016x" % got["set_hash"] == want["set_hash"]
+    assert got["nodes_total"] == want["nodes_total"]
+    nodes, count, hsh = _u64(got["nodes_v"]), _u64(got["count_v"]), _u64(got["hash_v"])
+    for v, nv, cv, hv in want["heaviest"]:
+        assert (int(nodes[v]), int(count[v]), "%016x" % int(hsh[v])) == (nv, cv, hv), v
+    assert _digest(nodes, count, hsh) == want["per_vertex_sha256"]
+    hist = {str(k): int(c) for k, c in enumerate(got["size_hist"]) if c}
+    assert hist == want["size_hist"]
+
+
+def test_rmat15_sampled_subproblems(m):
+    # the largest R-MAT scale whose enumeration a test can wait for (3.4e9
+    # cliques; each scale step multiplies them by 22-26), degeneracy ownership,
+    # in the tuned launch: totals are the sums of the per-subproblem triples,
+    # and a seeded sample plus the heaviest subproblems the oracle finishes in
+    # seconds equal the oracle's
+    from paper_2001_11433_amd import tuner
+    g = gg.rmat(15, 16, 0.57, 0.19, 0.19, seed=0)
+    kw = tuner.launch_kwargs(tuner.lookup(g, "degeneracy", family="rmat15"))
+    got = m.mce_static(g, rank="degeneracy", per_vertex=True, **kw)
+    nodes, count, hsh = _u64(got["nodes_v"]), _u64(got["count_v"]), _u64(got["hash_v"])
+    assert int(count.sum()) == got["count"]
+    assert int(nodes.sum()) == got["nodes_total"]
+    assert int(np.add.reduce(hsh, dtype=np.uint64)) == got["set_hash"]
+    rng = np.random.default_rng(15)
+    order = np.argsort(nodes)
+    heavy = order[nodes[order] <= 5_000_000][-12:]
+    sample = np.unique(np.concatenate([rng.choice(g.n, 384, replace=False), heavy])).astype(np.uint32)
+    want = O.mce_parmce(g, "degeneracy", verts=sample, threads=8)
     assert np.array_equal(nodes[sample], want.nodes_v)
     assert np.array_equal(count[sample], want.count_v)
     assert np.array_equal(hsh[sample], want.hash_v)

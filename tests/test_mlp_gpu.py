@@ -192,3 +192,39 @@ def test_learned_cost_ranks_subproblems_better_than_the_fallback_orders(cm):
         rho_tri = R.spearman(O.rank_metric(held, "triangle").astype(np.float64), t)
         print("seed %d: spearman learned %.3f, degree %.3f, triangle %.3f" % (seed, rho_learned, rho_degree, rho_tri))
         assert rho_learned > rho_degree and rho_learned > rho_tri
+
+
+@pytest.mark.parametrize("rank", ["degree", "degeneracy", "triangle", "peel"])
+def test_schedule_evaluated_inside_the_static_call(cm, rank):
+    # sched="mlp": features and the BF16 forward run inside mce_static (on a
+    # second stream, overlapping the build).  The costs that ordered the queue
+    # are exactly those of mce_features + mce_mlp_forward_bf16 called alone,
+    # and the results are those of every other order, with and without the
+    # root split and in the allocation-free call.
+    import paper_2001_11433_amd as m
+    model = cm.train_on_graphs([gg.rmat(10, seed=s) for s in (1, 2)], "degeneracy", epochs=60, lr=3e-3)["model"]
+    for g in (gg.rmat(11, seed=11), gg.plant_communities(gg.chung_lu(3000, 2.1, 8, seed=3), count=6, smin=20,
+                                                        smax=40, p=0.8, seed=4), gg.edgeless(5)):
+        dg = m.DeviceGraph.from_graph(g)
+        want = m.mce_static(dg, rank=rank, sched="degree", per_vertex=True)
+        ref = model.predict(m.mce_features(dg)).cpu().numpy()
+        for kw in ({}, {"split": 16}, {"noalloc": True}):
+            got = m.mce_static(dg, rank=rank, sched="mlp", model=model, sched_cost_out=True, per_vertex=True, **kw)
+            assert (got["count"], got["set_hash"], got["nodes_total"]) == \
+                (want["count"], want["set_hash"], want["nodes_total"]), kw
+            for k in ("nodes_v", "count_v", "hash_v"):
+                assert bool((got[k] == want[k]).all()), (kw, k)
+            assert np.array_equal(got["sched_cost"].cpu().numpy().view(np.uint32), ref.view(np.uint32)), kw
+
+
+def test_schedule_inside_the_call_needs_the_model(cm):
+    import ctypes
+    import paper_2001_11433_amd as m
+    dg = m.DeviceGraph.from_graph(gg.rmat(8, seed=1))
+    o = m._opts("degree")
+    o.sched = m.SCHEDS["mlp"]
+    res = m._Result()
+    rc = m.lib().mce_static(ctypes.byref(dg.csr()), m.RANKS["degree"], ctypes.byref(o), ctypes.byref(res), None, None)
+    assert rc == m.MCE_EINVAL
+    with pytest.raises(ValueError):
+        m.mce_static(dg, sched="mlp")
