@@ -56,9 +56,36 @@ struct Diag {
 // on donation attempts, so they live in the wave's LDS (lane 0 updates them)
 // instead of holding 28 scalar registers for the whole kernel, registers the
 // search loop needs.  Intervals are tallied as -start ... +end.
+// Per-task tallies.  The algorithmic op count of a node is
+// 3*s*w + 2*|ext|*w + 2*s with w fixed per subproblem, so the task keeps the
+// sums of s and |ext| and multiplies once at the end (ops()).
+struct Acc {
+  uint64_t tn, tc, th, ssum, esum;
+  uint64_t cssum, cesum;  // the part of ssum, esum from compact (re-based) nodes
+  __device__ uint64_t ops(uint32_t wv) const { return (3 * ssum + 2 * esum) * wv + 2 * ssum; }
+  // the same operations at the width the kernels execute: a wide node's rows
+  // span the subproblem's wp 64-bit cand words, a compact node's one
+  __device__ uint64_t exec_ops(uint32_t wp) const {
+    const uint64_t ws = ssum - cssum, we = esum - cesum;
+    return (3 * ws + 2 * we) * (2ULL * wp) + 2 * ws + (3 * cssum + 2 * cesum) * 2 + 2 * cssum;
+  }
+  // algorithmic LDS bytes of the formula 4 * w * (s + |ext|)
+  __device__ uint64_t lds_bytes(uint32_t wv) const { return 4ULL * wv * (ssum + esum); }
+  __device__ void add(const Acc& o) {
+    tn += o.tn;
+    tc += o.tc;
+    th += o.th;
+    ssum += o.ssum;
+    esum += o.esum;
+    cssum += o.cssum;
+    cesum += o.cesum;
+  }
+};
+
 struct WaveStat {
   uint64_t c, h, n, ops, xops, lds;
   Diag dg;
+  Acc cacc;  // the compact search's tallies of the current task
 };
 
 __device__ __forceinline__ void stat_add(uint64_t& f, uint64_t v) {
@@ -107,22 +134,6 @@ __device__ __forceinline__ void hist_flush(const EnumArgs& a, const uint64_t* lh
   if (c) atomicAdd((unsigned long long*)&a.hist[k < a.hist_len - 1 ? k : a.hist_len - 1], (unsigned long long)c);
 }
 
-// Per-task tallies.  The algorithmic op count of a node is
-// 3*s*w + 2*|ext|*w + 2*s with w fixed per subproblem, so the task keeps the
-// sums of s and |ext| and multiplies once at the end (ops()).
-struct Acc {
-  uint64_t tn, tc, th, ssum, esum;
-  uint64_t cssum, cesum;  // the part of ssum, esum from compact (re-based) nodes
-  __device__ uint64_t ops(uint32_t wv) const { return (3 * ssum + 2 * esum) * wv + 2 * ssum; }
-  // the same operations at the width the kernels execute: a wide node's rows
-  // span the subproblem's wp 64-bit cand words, a compact node's one
-  __device__ uint64_t exec_ops(uint32_t wp) const {
-    const uint64_t ws = ssum - cssum, we = esum - cesum;
-    return (3 * ws + 2 * we) * (2ULL * wp) + 2 * ws + (3 * cssum + 2 * cesum) * 2 + 2 * cssum;
-  }
-  // algorithmic LDS bytes of the formula 4 * w * (s + |ext|)
-  __device__ uint64_t lds_bytes(uint32_t wv) const { return 4ULL * wv * (ssum + esum); }
-};
 
 __device__ __forceinline__ uint64_t now() { return __builtin_readcyclecounter(); }
 
@@ -439,22 +450,40 @@ __device__ __forceinline__ uint32_t vbcnt_add(uint64_t x, uint32_t acc) {
 // are scalar; the clique-hash terms and the op terms of single-candidate
 // children are summed per lane (each lane adds the children it decides) and
 // reduced over the wave once per task.
+// The scalar counts are 32-bit (one instruction per add instead of two):
+// one expansion adds at most 129 to any of them, and they are flushed into the
+// wave's 64-bit task tallies (in LDS) at least every 2^16 + 1 expansions.
 struct VTally {
-  uint64_t tn, tc, ss, es;  // scalar
+  uint32_t tn, tc, ss, es;  // scalar
   uint64_t vh, vss;         // per lane
   __device__ void init() {
     tn = tc = ss = es = 0;
     vh = vss = 0;
   }
-  __device__ void flush(Acc& acc) const {
-    acc.tn += tn;
-    acc.tc += tc;
-    acc.th += wave_sum_u64(vh);
-    const uint64_t sc = ss + wave_sum_u64(vss);
-    acc.ssum += sc;
-    acc.esum += es;
-    acc.cssum += sc;
-    acc.cesum += es;
+  // the scalar counts only (in the search loop)
+  __device__ void flush_counts(Acc& la, Diag& dg) {
+    if (lane_id() == 0) {
+      la.tn += tn;
+      la.tc += tc;
+      la.ssum += ss;
+      la.esum += es;
+      la.cssum += ss;
+      la.cesum += es;
+      dg.cnodes += tn;
+    }
+    tn = tc = ss = es = 0;
+  }
+  // everything, the per-lane sums reduced over the wave (at the end)
+  __device__ void flush(Acc& la, Diag& dg) {
+    flush_counts(la, dg);
+    const uint64_t h = wave_sum_u64(vh);
+    const uint64_t v = wave_sum_u64(vss);
+    if (lane_id() == 0) {
+      la.th += h;
+      la.ssum += v;
+      la.cssum += v;
+    }
+    vh = vss = 0;
   }
 };
 
@@ -502,7 +531,7 @@ __device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
 template <bool EXCL, bool BIGK, class LT>
 __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
                             uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t D, uint64_t F, uint64_t zsum,
-                            bool expand, uint32_t kbase, uint32_t wv, Acc& acc, bool& can_donate, uint32_t& since,
+                            bool expand, uint32_t kbase, uint32_t wv, bool& can_donate, uint32_t& since,
                             const WideCtx* wide, Diag& dg) {
   const int lane = lane_id();
   uint32_t* const kG = BIGK ? gK : L.kG;
@@ -510,7 +539,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
   uint32_t kl = kbase;  // |K| of the current node
   bool framed = false;  // the current node's frame is the top of the stack
   stat_add(dg.t_compact, 0 - now());
-  const uint32_t dlim = 4 * a.donate_interval;
+  // search nodes between donation checks (also the tallies' flush interval)
+  const uint32_t dlim = a.donate_interval < (1u << 14) ? 4 * a.donate_interval : (1u << 16);
   const uint64_t lower = (1ULL << lane) - 1;  // the children before this lane's
   VTally T;
   T.init();
@@ -538,8 +568,8 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         const uint32_t row = mx & 0xFFu;
         const uint64_t prow = row < 64 ? readlane64(c.rowPP, row) : readlane64(c.rowXP, row & 63);
         ext = P & ~prow;
-        T.ss += (uint64_t)(__popcll(P) + __popcll(Xp) + __popcll(Xx));
-        T.es += (uint64_t)__popcll(ext);
+        T.ss += (uint32_t)(__popcll(P) + __popcll(Xp) + __popcll(Xx));
+        T.es += (uint32_t)__popcll(ext);
         // the child pass: lane q forms child q's cand and fini; the lane masks
         // of the children that are leaves or have one candidate decide them
         const uint64_t chm = EXCL ? (ext & ~F) : ext;  // excluded q join fini unvisited
@@ -557,7 +587,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         uint64_t cliqm = leafm & fm;
         uint64_t grandm = 0;
         uint32_t w = 0;
-        T.tn += (uint64_t)(__popcll(leafm) + __popcll(onem));
+        T.tn += (uint32_t)(__popcll(leafm) + __popcll(onem));
         if (onem) {
           // one candidate w: the child is one node; if no fini vertex is
           // adjacent to w (then the pivot, with ext empty) and the branch on w
@@ -570,13 +600,13 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
           if (EXCL) ok &= ~ballot((((F | c.rowEx) >> w) & 1ULL) != 0);
           grandm = ok;
           cliqm |= grandm;
-          T.tn += (uint64_t)__popcll(grandm);
-          T.es += (uint64_t)__popcll(onem & ~blk);
+          T.tn += (uint32_t)__popcll(grandm);
+          T.es += (uint32_t)__popcll(onem & ~blk);
           // the child's pivot step, counted like an expanded node's
           if ((onem >> lane) & 1ULL) T.vss += 1u + (uint32_t)__popcll(cXp) + (uint32_t)__popcll(cXx);
         }
         if (cliqm) {
-          T.tc += (uint64_t)__popcll(cliqm);
+          T.tc += (uint32_t)__popcll(cliqm);
           const uint64_t zw = grandm ? bpermute64(c.zP, w) : 0ULL;
           if ((cliqm >> lane) & 1ULL) {
             const bool two = (grandm >> lane) & 1ULL;
@@ -651,8 +681,11 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
     zsum += readlane64(c.zP, q);
     expand = true;
 
-    if (can_donate && ++since >= dlim) {
+    if (++since >= dlim) {
       since = 0;
+      T.flush_counts(L.st.cacc, dg);
+    }
+    if (can_donate && since == 0) {
       stat_add(dg.t_donate, 0 - now());
       for (uint32_t piece = 0, want = starving(a) ? 1u : 0u; piece < want && can_donate; ++piece) {
         stat_add(dg.attempts, 1);
@@ -698,8 +731,7 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
       stat_add(dg.t_donate, now());
     }
   }
-  stat_add(dg.cnodes, T.tn);
-  T.flush(acc);
+  T.flush(L.st.cacc, dg);
   stat_add(dg.t_compact, now());
 }
 
@@ -955,10 +987,10 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
       __syncthreads();
       if (lane == 0) pool_push(a, blk);
       if (bigk)
-        compact_dfs<EXCL, true>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, acc, can_donate,
+        compact_dfs<EXCL, true>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, can_donate,
                                 since, nullptr, dg);
       else
-        compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, acc, can_donate,
+        compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, can_donate,
                                  since, nullptr, dg);
     } else {
       const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
@@ -1136,10 +1168,10 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
                   const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
                   stat_add(dg.t_rebase, now() - tr);
                   if (bigk)
-                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv,
                                             can_donate, since, &wctx, dg);
                   else
-                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, acc,
+                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv,
                                              can_donate, since, &wctx, dg);
                 }
                 rebased = true;
@@ -1244,18 +1276,20 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
       if (lane == 0) atomicOr((unsigned long long*)&a.ctl[CTL_FLAGS], 1ULL);
     }
     if (lane == 0) {
-      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
-      if (a.count_v && acc.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)acc.tc);
-      if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
+      // the wide nodes' tallies (registers) plus the compact search's (LDS)
+      Acc t = acc;
+      t.add(L.st.cacc);
+      L.st.cacc = Acc{};
+      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)t.tn);
+      if (a.count_v && t.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)t.tc);
+      if (a.hash_v && t.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)t.th);
       fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
-    }
-    if (lane == 0) {
-      L.st.n += acc.tn;
-      L.st.c += acc.tc;
-      L.st.h += acc.th;
-      L.st.ops += acc.ops(wv);
-      L.st.xops += acc.exec_ops((p + 63) >> 6);
-      L.st.lds += acc.lds_bytes(wv);
+      L.st.n += t.tn;
+      L.st.c += t.tc;
+      L.st.h += t.th;
+      L.st.ops += t.ops(wv);
+      L.st.xops += t.exec_ops((p + 63) >> 6);
+      L.st.lds += t.lds_bytes(wv);
     }
   }
   hist_flush(a, L.hist);
@@ -1304,7 +1338,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     stat_add(dg.tasks, 1);
     const bool pooled = (ref >> 63) != 0;
     const uint64_t idx = ref & 0xFFFFFFFFULL;
-    Acc acc = {0, 0, 0, 0, 0, 0, 0};
     Compact c;
     uint64_t P, Xp = 0, Xx, ext = 0, D = 0, zsum, F;
     uint32_t klen, s;
@@ -1322,21 +1355,21 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;
-    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, D, F, zsum, !pooled, klen, wv, acc, can_donate,
+    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, D, F, zsum, !pooled, klen, wv, can_donate,
                              since, (const WideCtx*)nullptr, dg);
     if (lane == 0) {
-      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)acc.tn);
-      if (a.count_v && acc.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)acc.tc);
-      if (a.hash_v && acc.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)acc.th);
+      const Acc t = L.st.cacc;
+      L.st.cacc = Acc{};
+      if (a.nodes_v) atomicAdd((unsigned long long*)&a.nodes_v[s], (unsigned long long)t.tn);
+      if (a.count_v && t.tc) atomicAdd((unsigned long long*)&a.count_v[s], (unsigned long long)t.tc);
+      if (a.hash_v && t.th) atomicAdd((unsigned long long*)&a.hash_v[s], (unsigned long long)t.th);
       fetch_add(&a.ctl[CTL_PENDING], ~0ULL);  // this task is done
-    }
-    if (lane == 0) {
-      L.st.n += acc.tn;
-      L.st.c += acc.tc;
-      L.st.h += acc.th;
-      L.st.ops += acc.ops(wv);
-      L.st.xops += acc.exec_ops((p + 63) >> 6);
-      L.st.lds += acc.lds_bytes(wv);
+      L.st.n += t.tn;
+      L.st.c += t.tc;
+      L.st.h += t.th;
+      L.st.ops += t.ops(wv);
+      L.st.xops += t.exec_ops((p + 63) >> 6);
+      L.st.lds += t.lds_bytes(wv);
     }
   }
   hist_flush(a, L.hist);
