@@ -571,6 +571,8 @@ def main():
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / INT32_VALU_PEAK,
                      "traffic": measured_traffic(r0["alg_ops"]),
                      "traffic_unit": "bytes per call (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)",
+                     "algorithmic_bytes": r0["arena_bytes"],
+                     "algorithmic_bytes_note": "the subproblems' bit rows and ids, each read once",
                      "kernel": "k_enum + k_compact (the enumeration: both launches)",
                      "ops_per_launch": r0["alg_ops"],
                      "issue": measured_issue(),

@@ -127,7 +127,10 @@ typedef struct {
   uint32_t compact_waves_per_cu;
   uint32_t inline_compact;
   /* Order of the handed-off nodes in the compact kernel's queue: 0 = as
-   * produced, 1 = largest candidate set first.  Never changes results. */
+   * produced, 1 = largest candidate set first, 2 = grouped by subproblem
+   * (records that gather rows of the same subproblem are claimed together,
+   * so the rows are read from L2 rather than from HBM).  Never changes
+   * results. */
   uint32_t compact_order;
   /* Bit rows of a wide subproblem (over 64 candidates) in LDS: per-wave row
    * cache of this many 64-bit words (0 = none, at most 4096).  A subproblem
@@ -176,6 +179,8 @@ typedef struct {
                            compact 64 + 64 universe */
   uint64_t lds_bytes;   /* algorithmic LDS bytes of the search: per node 4 * w * (s + |ext|), w
                            and s as in alg_ops (the compact kernel keeps its rows in registers) */
+  uint64_t arena_bytes; /* the subproblems' bit rows and vertex ids the search reads: its
+                           algorithmic device-memory bytes (each read once) */
 } mce_result;
 
 /* Clique output in CSR form: clique i is vert[off[i] .. off[i+1]), vertices

@@ -51,7 +51,7 @@ class _Result(ctypes.Structure):
                 ("alg_ops", ctypes.c_uint64), ("rank_ms", ctypes.c_double), ("build_ms", ctypes.c_double), ("enum_ms", ctypes.c_double),
                 ("retries", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("diag", ctypes.c_uint64 * 8),
                 ("compact_ms", ctypes.c_double), ("handed", ctypes.c_uint64), ("exec_ops", ctypes.c_uint64),
-                ("lds_bytes", ctypes.c_uint64)]
+                ("lds_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64)]
 
 
 class _CliqueBuf(ctypes.Structure):

@@ -373,17 +373,20 @@ int run_enum(EnumJob& j, EnumWork& w, hipStream_t s, uint64_t* ctl, uint32_t* re
       a.qcap = qcap2;
       MCE_TRY_HIP(dev_zero(w.queue.p, qcap2 * sizeof(uint64_t), s));
       const uint32_t* order = nullptr;
-      if (opts.compact_order == 1) {
-        // largest candidate set first (then largest fini)
+      if (opts.compact_order == 1 || opts.compact_order == 2) {
+        // 1: largest candidate set first (then largest fini); 2: grouped by
+        // subproblem (its records gather the same rows), larger first within
+        const uint32_t by_sub = opts.compact_order == 2 ? 1u : 0u;
         MCE_TRY(w.hkeys.ensure(nh * 8));
         MCE_TRY(w.hkeys2.ensure(nh * 8));
         MCE_TRY(w.hvals.ensure(nh * 4));
         MCE_TRY(w.hvals2.ensure(nh * 4));
-        MCE_TRY_HIP(launch_hand_keys(nh, a.hand, a.hand_idx, w.hkeys.as<uint64_t>(), w.hvals.as<uint32_t>(), s));
+        MCE_TRY_HIP(launch_hand_keys(nh, a.hand, a.hand_idx, by_sub, w.hkeys.as<uint64_t>(), w.hvals.as<uint32_t>(),
+                                     s));
         uint64_t* sk;
         uint32_t* sv;
         MCE_TRY(device_sort_desc(w.hkeys.as<uint64_t>(), w.hvals.as<uint32_t>(), w.hkeys2.as<uint64_t>(),
-                                 w.hvals2.as<uint32_t>(), nh, w.sort_tmp, w.sort_bytes, s, &sk, &sv, 16));
+                                 w.hvals2.as<uint32_t>(), nh, w.sort_tmp, w.sort_bytes, s, &sk, &sv, by_sub ? 48 : 16));
         order = sv;
       }
       MCE_TRY_HIP(launch_queue_fill_hand(nh, order, a.queue, s));
@@ -720,6 +723,7 @@ int static_impl(const mce_csr* g, mce_rank rank, const mce_opts& opts, mce_resul
   out->alg_ops = ctl[CTL_OPS];
   out->exec_ops = ctl[CTL_OPS_EXEC];
   out->lds_bytes = ctl[CTL_LDS_BYTES];
+  out->arena_bytes = arena_words * sizeof(uint64_t) + gid_words * sizeof(uint32_t);
   for (int k = 0; k < 8; ++k) out->diag[k] = ctl[CTL_DIAG + k];
   out->compact_ms = job.hand_ms;
   out->handed = job.handed;

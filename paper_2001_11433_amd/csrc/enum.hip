@@ -1395,11 +1395,13 @@ __global__ void k_queue_fill_hand(uint64_t nh, const uint32_t* __restrict__ orde
 }
 
 __global__ void k_hand_keys(uint64_t nh, const uint64_t* __restrict__ hand, const uint32_t* __restrict__ hand_idx,
-                            uint64_t* keys, uint32_t* vals) {
+                            uint32_t by_sub, uint64_t* keys, uint32_t* vals) {
   uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= nh) return;
   const uint64_t h = hand[(uint64_t)hand_idx[i] * 8];
-  keys[i] = (((h >> 32) & 0xFF) << 8) | ((h >> 40) & 0xFF);
+  const uint64_t size = (((h >> 32) & 0xFF) << 8) | ((h >> 40) & 0xFF);
+  // by subproblem: the records that gather the same rows are claimed together
+  keys[i] = by_sub ? (((h & 0xFFFFFFFFULL) << 16) | size) : size;
   vals[i] = (uint32_t)i;
 }
 
@@ -1421,10 +1423,10 @@ hipError_t launch_queue_fill_hand(uint64_t nh, const uint32_t* order, uint64_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint64_t* keys,
+hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint32_t by_sub, uint64_t* keys,
                             uint32_t* vals, hipStream_t s) {
   if (nh == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hand_keys, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, hand, hand_idx, keys,
+  hipLaunchKernelGGL(k_hand_keys, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, nh, hand, hand_idx, by_sub, keys,
                      vals);
   return hipGetLastError();
 }

@@ -312,7 +312,7 @@ hipError_t launch_enum(const EnumArgs& a, uint32_t grid, bool exclusion, hipStre
 hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s);
 hipError_t launch_queue_fill_hand(uint64_t nh, const uint32_t* order, uint64_t* queue, hipStream_t s);
 // Sort keys of the handoff records: candidate count, then fini count.
-hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint64_t* keys,
+hipError_t launch_hand_keys(uint64_t nh, const uint64_t* hand, const uint32_t* hand_idx, uint32_t by_sub, uint64_t* keys,
                             uint32_t* vals, hipStream_t s);
 hipError_t launch_finish_offsets(uint64_t* off, uint64_t n_cliques, uint64_t n_verts, hipStream_t s);
 hipError_t launch_pool_init(uint32_t* next, uint64_t blocks, hipStream_t s);

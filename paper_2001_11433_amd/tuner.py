@@ -38,11 +38,15 @@ GRID = (
     ("compact", ("inline", 8, 12, 20, 28)),
     ("waves_per_cu", (2, 4, 8, 16)),
 )
-SPACE = (("donate_interval", (256, 1024, 4096, 16384)), ("compact_order", (0, 1)),
+SPACE = (("donate_interval", (256, 1024, 4096, 16384)), ("compact_order", (0, 1, 2)),
          ("lds_row_words", (0, 1024, 2048, 4096)), ("frame_cap", (32, 128, 512)))
 DEFAULT = {"waves_per_cu": 8, "donate_interval": 1024, "compact": 20, "compact_order": 0, "lds_row_words": 0,
            "frame_cap": 128}
 SAMPLES = 3
+NEAR = 0.015  # relative time difference treated as a tie
+# a smaller grid where the full one is known not to matter (the 1M-vertex
+# graph wants the compact kernel at high occupancy and few k_enum waves)
+GRID_FOR = {"cl1m-communities": (("compact", (20, 28)), ("waves_per_cu", (4, 8)))}
 
 
 def launch_kwargs(knobs: dict) -> dict:
@@ -141,6 +145,18 @@ def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, s
             t = run(k)
             if t < best_t:
                 best, best_t = k, t
+    # the by-subproblem order at the best point found, for the tie rule below
+    if best.get("compact") != "inline" and best.get("compact_order") != 2 and not out_of_time() and \
+            any(name == "compact_order" for name, _ in space):
+        run(dict(best, compact_order=2))
+    # near-ties (within NEAR of the fastest, i.e. run-to-run noise) go to the
+    # setting that groups the compact records by subproblem: same speed, far
+    # fewer HBM bytes (its records gather their rows from L2)
+    near = [t for t in trials if t["enum_ms"] <= best_t * (1 + NEAR) and t.get("compact_order") == 2]
+    if near and best.get("compact_order") != 2:
+        pick = min(near, key=lambda t: t["enum_ms"])
+        best = {k: v for k, v in pick.items() if k not in ("enum_ms", "samples")}
+        best_t = pick["enum_ms"]
     result = {"best": best, "enum_ms": best_t, "trials": trials, "samples": samples}
     if path:
         table = load_table(path)
@@ -243,7 +259,7 @@ def tune_workloads(out_path: str = TABLE, which: Sequence[str] = ("rmat14", "rma
             table = load_table(out_path)
             table["family:" + name] = r
         else:
-            r = tune(g, rank, path=out_path, log=log)
+            r = tune(g, rank, path=out_path, log=log, grid=GRID_FOR.get(name, GRID))
             table = load_table(out_path)
             table["family:" + name] = r
             if name == "rmat15":
