@@ -8,8 +8,9 @@ The oracle cannot enumerate these graphs whole in test time, so:
     triple, the heaviest subproblems, the clique-size distribution); and the
     per-subproblem triples (search nodes, cliques, clique-set hash) of a seeded
     sample of vertices against the oracle run in the test;
-  * R-MAT scale 15 (degeneracy ownership): the same sampled per-subproblem
-    check; scale 18: rank metrics (degree, core number, triangles, peel
+  * R-MAT scale 14 (degeneracy ownership): the whole graph against the
+    oracle's full ParMCE (tests/golden/rmat14_totals.json, same fields);
+    scale 15: the sampled per-subproblem check; scale 18: rank metrics (degree, core number, triangles, peel
     rounds) of every vertex against the oracle (its enumeration is far beyond
     reach);
   * the 500k-vertex Chung-Lu stream: all eight result fields of all 200
@@ -81,16 +82,17 @@ def test_cl1m_communities_whole_graph_against_the_oracle(m):
     # oracle's full ParMCE (tests/golden/c3_totals.json, oracle/make_golden.py):
     # totals, the per-subproblem triples of all 10^6 vertices (by digest), the
     # heaviest subproblems one by one, and the clique-size distribution
-    from paper_2001_11433_amd import tuner
-    path = os.path.join(GOLDEN, "c3_totals.json")
-    if not os.path.exists(path):
-        pytest.skip("tests/golden/c3_totals.json not written yet (oracle/make_golden.py c3, hours of CPU)")
-    with open(path) as f:
-        want = json.load(f)
     g = gg.plant_communities(gg.chung_lu(1_000_000, 2.1, 20, seed=0), count=500, smin=30, smax=80, p=0.9, seed=1)
+    _whole_graph_against_golden(m, g, "degree", "cl1m-communities", "c3_totals.json")
+
+
+def _whole_graph_against_golden(m, g, rank, family, name):
+    from paper_2001_11433_amd import tuner
+    with open(os.path.join(GOLDEN, name)) as f:
+        want = json.load(f)
     assert (g.n, g.m) == (want["n"], want["m"])
-    kw = tuner.launch_kwargs(tuner.lookup(g, "degree", family="cl1m-communities"))
-    got = m.mce_static(g, rank="degree", per_vertex=True, size_hist=4097, **kw)
+    kw = tuner.launch_kwargs(tuner.lookup(g, rank, family=family))
+    got = m.mce_static(g, rank=rank, per_vertex=True, size_hist=4097, **kw)
     assert got["count"] == want["count"]
     assert "%016x" % got["set_hash"] == want["set_hash"]
     assert got["nodes_total"] == want["nodes_total"]
@@ -100,6 +102,14 @@ def test_cl1m_communities_whole_graph_against_the_oracle(m):
     assert _digest(nodes, count, hsh) == want["per_vertex_sha256"]
     hist = {str(k): int(c) for k, c in enumerate(got["size_hist"]) if c}
     assert hist == want["size_hist"]
+
+
+def test_rmat14_whole_graph_against_the_oracle(m):
+    # the R-MAT family under degeneracy ownership, whole graph, against the
+    # oracle's full ParMCE (tests/golden/rmat14_totals.json); one subproblem
+    # holds most of its search nodes, which donation spreads over the waves
+    g = gg.rmat(14, 16, 0.57, 0.19, 0.19, seed=0)
+    _whole_graph_against_golden(m, g, "degeneracy", "rmat14", "rmat14_totals.json")
 
 
 def test_rmat15_sampled_subproblems(m):
