@@ -38,6 +38,7 @@ using namespace mce;
 struct BatchSlot {
   DevBuf new_off, new_vert;  // cliques of the edge subproblems (the search's output)
   DevBuf dk, hk;             // the batch's sorted directed keys (u*n + v, both orientations) and edge keys
+  DevBuf hoff;               // hoff[x]: first of vertex x's keys in dk (x = 0..n)
   DevBuf del_off, del_vert;  // the subsumed pass's de-duplicated cliques
   uint64_t cap_nc = 0, cap_nv = 0;
   bool remove = false;
@@ -163,33 +164,42 @@ __device__ __forceinline__ uint64_t lower_bound_u32(const uint32_t* a, uint64_t 
   return lo;
 }
 
-__global__ void k_newdeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ dkeys, uint64_t nd,
+// Start of every vertex's keys in the sorted directed batch keys (x * n + w):
+// hoff[x] = the first key >= x * n, for x = 0..n (hoff[n] = nd).  Built once
+// per batch, it replaces two binary searches per lookup in the kernels below.
+__global__ void k_hoff(uint64_t n, const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* hoff) {
+  const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (x <= n) hoff[x] = lower_bound_u64(dkeys, nd, x * n);
+}
+
+__global__ void k_newdeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ hoff,
                          uint64_t* degw) {
   uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint64_t lo = hoff[v], hi = hoff[v + 1];
   degw[v] = rp[v + 1] - rp[v] + (hi - lo);
 }
 
 __global__ void k_rp_tail(uint64_t n, uint64_t* rpn, const uint64_t* degw) { rpn[n] = rpn[n - 1] + degw[n - 1]; }
 
 // G - H: degrees after the deletions (every batch pair is an edge of G).
-__global__ void k_deldeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ dkeys, uint64_t nd,
+__global__ void k_deldeg(uint64_t n, const uint64_t* __restrict__ rp, const uint64_t* __restrict__ hoff,
                          uint64_t* degw) {
   uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint64_t lo = hoff[v], hi = hoff[v + 1];
   degw[v] = rp[v + 1] - rp[v] - (hi - lo);
 }
 
 // One wave per vertex: its row without the deleted neighbours, order kept.
 __global__ void __launch_bounds__(256) k_remove_rows(uint64_t n, const uint64_t* __restrict__ rp,
                                                      const uint32_t* __restrict__ col, const uint64_t* __restrict__ dkeys,
-                                                     uint64_t nd, const uint64_t* __restrict__ rpn, uint32_t* coln) {
+                                                     const uint64_t* __restrict__ hoff, const uint64_t* __restrict__ rpn,
+                                                     uint32_t* coln) {
   const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = lane_id();
   if (v >= n) return;
-  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint64_t lo = hoff[v], hi = hoff[v + 1];
   const uint32_t* row = col + rp[v];
   const uint64_t d = rp[v + 1] - rp[v];
   uint32_t* out = coln + rpn[v];
@@ -211,11 +221,12 @@ __global__ void __launch_bounds__(256) k_remove_rows(uint64_t n, const uint64_t*
 // One wave per vertex: merge the old row with the vertex's new neighbours.
 __global__ void __launch_bounds__(256) k_merge_rows(uint64_t n, const uint64_t* __restrict__ rp,
                                                     const uint32_t* __restrict__ col, const uint64_t* __restrict__ dkeys,
-                                                    uint64_t nd, const uint64_t* __restrict__ rpn, uint32_t* coln) {
+                                                    const uint64_t* __restrict__ hoff, const uint64_t* __restrict__ rpn,
+                                                    uint32_t* coln) {
   const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = lane_id();
   if (v >= n) return;
-  const uint64_t lo = lower_bound_u64(dkeys, nd, v * n), hi = lower_bound_u64(dkeys, nd, (v + 1) * n);
+  const uint64_t lo = hoff[v], hi = hoff[v + 1];
   const uint64_t t = hi - lo;
   const uint32_t* row = col + rp[v];
   const uint64_t d = rp[v + 1] - rp[v];
@@ -301,8 +312,8 @@ __global__ void __launch_bounds__(256) k_edge_rows(uint64_t m, const uint32_t* _
                                                    const uint32_t* __restrict__ col, const uint32_t* __restrict__ P,
                                                    const uint64_t* __restrict__ off, const uint64_t* __restrict__ goff,
                                                    const uint32_t* __restrict__ gids, const uint64_t* __restrict__ dkeys,
-                                                   const uint32_t* __restrict__ didx, uint64_t nd, uint64_t n,
-                                                   uint64_t* arena) {
+                                                   const uint32_t* __restrict__ didx, const uint64_t* __restrict__ hoff,
+                                                   uint64_t n, uint64_t* arena) {
   // wave (edge e, blockIdx.y): candidates [y * kEdgeRowsPerWave, ...)
   const uint64_t e = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = lane_id();
@@ -323,7 +334,7 @@ __global__ void __launch_bounds__(256) k_edge_rows(uint64_t m, const uint32_t* _
       const int64_t b = bsearch_u32(g, p, col[j]);
       if (b >= 0) atomicOr((unsigned long long*)&rowP[(uint64_t)(b >> 6) * p + a], 1ULL << (b & 63));
     }
-    const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)q * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(q + 1) * n);
+    const uint64_t lo = hoff[q], hi = hoff[q + 1];
     for (uint64_t k = lo + lane; k < hi; k += kWave) {
       if (didx[k] >= e) continue;  // only e_j with j < i are excluded
       const uint32_t w = (uint32_t)(dkeys[k] % n);
@@ -344,13 +355,54 @@ __global__ void k_iota32(uint64_t n, uint32_t* a) {
 
 // -- 4. subsumed cliques --------------------------------------------------------
 
+// Candidates found by one wave are staged here and reserved in the output
+// with one atomic per kStageN (instead of one per candidate: a single counter
+// hit by every wave of the GPU is what bounds the pass otherwise).
+constexpr uint32_t kStageN = 32, kStageV = 512;
+
 template <uint32_t MAXS, uint32_t MAXP>
 struct SubLds {
   uint32_t c[kSubMaxK];
   uint64_t pairs[MAXP];
   uint64_t S[2][MAXS];
   uint32_t np, ns;
+  uint32_t sv[kStageV];  // staged candidates' vertices, back to back
+  uint32_t sk[kStageN];  // their sizes
+  uint64_t sh[kStageN];  // their clique hash terms
+  uint32_t snn, snv;     // staged candidates and vertices
 };
+
+// Writes the staged candidates out (one reservation for all of them) and
+// empties the stage.  Every lane calls it.
+template <class SL>
+__device__ void stage_flush(SL& L, uint64_t* sctl, uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
+                            uint64_t cap_c, uint64_t cap_v) {
+  const int lane = lane_id();
+  __syncthreads();
+  const uint32_t nn = L.snn, nv = L.snv;
+  if (nn == 0) return;
+  uint64_t old = 0;
+  if (lane == 0) old = atomicAdd((unsigned long long*)&sctl[0], (unsigned long long)(((uint64_t)nn << 32) | nv));
+  old = readlane64(old, 0);
+  const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
+  if (id + nn > cap_c || pos + nv > cap_v) {
+    if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 4ULL);
+  } else {
+    for (uint32_t j = lane; j < nv; j += kWave) cand_vert[pos + j] = L.sv[j];
+    const uint32_t kk = lane < (int)nn ? L.sk[lane] : 0u;
+    const uint32_t incl = wave_incl_scan_u32(kk);
+    if (lane < (int)nn) {
+      cand_off[id + lane] = pos + incl - kk;
+      cand_hash[id + lane] = L.sh[lane];
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    L.snn = 0;
+    L.snv = 0;
+  }
+  __syncthreads();
+}
 
 // Subsumed-clique candidates of the new cliques (or of those listed in
 // `list`, `*nlist` of them).  A clique whose batch edges or subsets exceed
@@ -367,12 +419,17 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
                                                  const uint32_t* __restrict__ nvert, uint64_t n,
                                                  const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
                                                  const uint64_t* __restrict__ hkeys, uint64_t nh,
-                                                 const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* sctl,
+                                                 const uint64_t* __restrict__ dkeys, const uint64_t* __restrict__ hoff, uint64_t* sctl,
                                                  uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
                                                  uint64_t cap_c, uint64_t cap_v) {
   __shared__ SubLds<MAXS, MAXP> L;
   const int lane = threadIdx.x;
   const uint64_t items = list ? *nlist : nnew;
+  if (lane == 0) {
+    L.snn = 0;
+    L.snv = 0;
+  }
+  __syncthreads();
   for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const uint64_t ci = list ? list[it] : it;
     const uint64_t b0 = noff[ci];
@@ -392,7 +449,7 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
     // batch edges inside c: lane j walks the new neighbours of c[j]
     if (lane < (int)k) {
       const uint32_t x = L.c[lane];
-      const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)x * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(x + 1) * n);
+      const uint64_t lo = hoff[x], hi = hoff[x + 1];
       for (uint64_t t = lo; t < hi; ++t) {
         const uint32_t w = (uint32_t)(dkeys[t] % n);
         if (w <= x) continue;  // each pair once
@@ -501,26 +558,26 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
         }
       }
       if (extends) continue;
-      // c' is a maximal clique of G: a subsumed-clique candidate
+      // c' is a maximal clique of G: a subsumed-clique candidate, staged
       const uint32_t kk = (uint32_t)__popcll(sm);
-      uint64_t old = 0;
-      if (lane == 0) old = atomicAdd((unsigned long long*)&sctl[0], (unsigned long long)((1ULL << 32) | kk));
-      old = readlane64(old, 0);
-      const uint64_t id = old >> 32, pos = old & 0xFFFFFFFFULL;
-      if (id >= cap_c || pos + kk > cap_v) {
-        if (lane == 0) atomicOr((unsigned long long*)&sctl[1], 4ULL);
-        continue;
-      }
+      if (L.snn == kStageN || L.snv + kk > kStageV)
+        stage_flush(L, sctl, cand_off, cand_vert, cand_hash, cap_c, cap_v);
+      const uint32_t at = L.snv;
       const uint64_t below = mem ? __popcll(sm & ((1ULL << lane) - 1)) : 0;
-      if (mem) cand_vert[pos + below] = x;
+      if (mem) L.sv[at + below] = x;
       const uint64_t z = wave_sum_u64(mem ? mix64(x) : 0);
+      __syncthreads();
       if (lane == 0) {
-        cand_off[id] = pos;
-        cand_hash[id] = clique_term(z, kk);
+        L.sk[L.snn] = kk;
+        L.sh[L.snn] = clique_term(z, kk);
+        L.snn += 1;
+        L.snv = at + kk;
       }
+      __syncthreads();
     }
     __syncthreads();
   }
+  stage_flush(L, sctl, cand_off, cand_vert, cand_hash, cap_c, cap_v);
 }
 
 // Subsumed-clique candidates of new cliques with more than kSubMaxK vertices
@@ -542,7 +599,7 @@ __global__ void __launch_bounds__(64) k_subsumed_big(const uint32_t* __restrict_
                                                      const uint64_t* __restrict__ noff,
                                                      const uint32_t* __restrict__ nvert, uint64_t n,
                                                      const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
-                                                     const uint64_t* __restrict__ dkeys, uint64_t nd, uint64_t* sctl,
+                                                     const uint64_t* __restrict__ dkeys, const uint64_t* __restrict__ hoff, uint64_t* sctl,
                                                      uint64_t* cand_off, uint32_t* cand_vert, uint64_t* cand_hash,
                                                      uint64_t cap_c, uint64_t cap_v) {
   __shared__ BigLds L;
@@ -569,7 +626,7 @@ __global__ void __launch_bounds__(64) k_subsumed_big(const uint32_t* __restrict_
     // batch edges inside c (each pair once, from its smaller vertex)
     for (uint32_t j = lane; j < k; j += kWave) {
       const uint32_t x = L.c[j];
-      const uint64_t lo = lower_bound_u64(dkeys, nd, (uint64_t)x * n), hi = lower_bound_u64(dkeys, nd, (uint64_t)(x + 1) * n);
+      const uint64_t lo = hoff[x], hi = hoff[x + 1];
       for (uint64_t t = lo; t < hi; ++t) {
         const uint32_t w = (uint32_t)(dkeys[t] % n);
         if (w <= x) continue;
@@ -946,6 +1003,10 @@ int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t r
   MCE_TRY(b.hk.ensure(m * 8));
   MCE_TRY_HIP(hipMemcpyAsync(b.dk.p, dk, nd * 8, hipMemcpyDeviceToDevice, s));
   MCE_TRY_HIP(hipMemcpyAsync(b.hk.p, hk, m * 8, hipMemcpyDeviceToDevice, s));
+  MCE_TRY(b.hoff.ensure((n + 1) * 8));
+  hipLaunchKernelGGL(k_hoff, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, n, dk, nd, b.hoff.as<uint64_t>());
+  MCE_TRY_HIP(hipGetLastError());
+  const uint64_t* hof = b.hoff.as<uint64_t>();
 
   // 2. the graph after the batch, G + H or G - H, into a free buffer
   const int nxt = free_buffer(st, keep);
@@ -956,16 +1017,16 @@ int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t r
   uint64_t* rpn = st->rp[nxt].as<uint64_t>();
   uint32_t* coln = st->col[nxt].as<uint32_t>();
   if (remove)
-    hipLaunchKernelGGL(k_deldeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
+    hipLaunchKernelGGL(k_deldeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, hof, st->degw.as<uint64_t>());
   else
-    hipLaunchKernelGGL(k_newdeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dk, nd, st->degw.as<uint64_t>());
+    hipLaunchKernelGGL(k_newdeg, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, hof, st->degw.as<uint64_t>());
   MCE_TRY_HIP(hipGetLastError());
   MCE_TRY(device_exclusive_scan(st->degw.as<uint64_t>(), rpn, n, st->scan_tmp, st->scan_bytes, s));
   hipLaunchKernelGGL(k_rp_tail, dim3(1), dim3(1), 0, s, n, rpn, st->degw.as<uint64_t>());
   if (remove)
-    hipLaunchKernelGGL(k_remove_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
+    hipLaunchKernelGGL(k_remove_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, hof, rpn, coln);
   else
-    hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, nd, rpn, coln);
+    hipLaunchKernelGGL(k_merge_rows, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, dk, hof, rpn, coln);
   MCE_TRY_HIP(hipGetLastError());
   // the search runs on the graph that holds H
   const uint64_t* srp = remove ? rp : rpn;
@@ -1009,7 +1070,7 @@ int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t r
   const uint32_t row_chunks = (uint32_t)std::max<uint64_t>((stats[0] + kEdgeRowsPerWave - 1) / kEdgeRowsPerWave, 1);
   hipLaunchKernelGGL(k_edge_rows, dim3(blocks_for(m * 64, 256), row_chunks), dim3(256), 0, s, m, st->eu.as<uint32_t>(),
                      st->ev.as<uint32_t>(), srp, scol, st->p.as<uint32_t>(), st->off.as<uint64_t>(),
-                     st->goff.as<uint64_t>(), st->gids.as<uint32_t>(), dk, di, nd, n, st->arena.as<uint64_t>());
+                     st->goff.as<uint64_t>(), st->gids.as<uint32_t>(), dk, di, hof, n, st->arena.as<uint64_t>());
   hipLaunchKernelGGL(k_iota32, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, st->order.as<uint32_t>());
   MCE_TRY_HIP(hipGetLastError());
 
@@ -1092,6 +1153,7 @@ int phase_b(imce_state* st, int si, hipStream_t s) {
   const uint32_t* mcol = st->col[mb].as<uint32_t>();
   const uint64_t* hk = b.hk.as<uint64_t>();
   const uint64_t* dk = b.dk.as<uint64_t>();
+  const uint64_t* hof = b.hoff.as<uint64_t>();
   Events evs;
   MCE_TRY(evs.init());
   MCE_TRY_HIP(hipEventRecord(evs.e[0], s));
@@ -1117,17 +1179,17 @@ int phase_b(imce_state* st, int si, hipStream_t s) {
       uint32_t* big = st->sbig.as<uint32_t>();
       hipLaunchKernelGGL((k_subsumed<kSubFastS, kSubFastPairs>), dim3(grid), dim3(64), 0, s, nc_new, nullptr, nullptr,
                          defer, big, b.new_off.as<uint64_t>(), b.new_vert.as<uint32_t>(), n, mrp, mcol, hk, m, dk,
-                         nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
+                         hof, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       hipLaunchKernelGGL((k_subsumed<kSubMaxS, kSubMaxPairs>), dim3(1024), dim3(64), 0, s, nc_new, defer, sc + 2,
                          nullptr, nullptr, b.new_off.as<uint64_t>(), b.new_vert.as<uint32_t>(), n, mrp, mcol, hk, m,
-                         dk, nd, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
+                         dk, hof, sc, st->cand_off.as<uint64_t>(), st->cand_vert.as<uint32_t>(),
                          st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
       // new cliques above kSubMaxK vertices (rare: a batch edge inside a very large clique)
       hipLaunchKernelGGL(k_subsumed_big, dim3(256), dim3(64), 0, s, big, sc + 3, b.new_off.as<uint64_t>(),
-                         b.new_vert.as<uint32_t>(), n, mrp, mcol, dk, nd, sc, st->cand_off.as<uint64_t>(),
+                         b.new_vert.as<uint32_t>(), n, mrp, mcol, dk, hof, sc, st->cand_off.as<uint64_t>(),
                          st->cand_vert.as<uint32_t>(), st->cand_hash.as<uint64_t>(), st->cap_cc, st->cap_cv);
       MCE_TRY_HIP(hipGetLastError());
     }
@@ -1340,7 +1402,7 @@ uint64_t state_bytes(const imce_state* st) {
         &st->sdefer, &st->sbig})
     t += b->bytes;
   for (const BatchSlot& b : st->slot)
-    for (const DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.del_off, &b.del_vert}) t += d->bytes;
+    for (const DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.hoff, &b.del_off, &b.del_vert}) t += d->bytes;
   for (const DevBuf* d : {&st->ew.queue, &st->ew.ctl, &st->ew.pool, &st->ew.pool_next, &st->ew.stacks, &st->ew.hand,
                           &st->ew.hand_idx, &st->ew.hkeys, &st->ew.hkeys2, &st->ew.hvals, &st->ew.hvals2,
                           &st->ew.kbig})
@@ -1375,7 +1437,7 @@ uint64_t batch_bytes(const imce_state* st, uint64_t rho) {
   t += grow(st->arena, m * per_edge) + grow(st->gids, m * 256);
   // slot buffers of one batch (the first batch sizes them)
   const BatchSlot& b = st->slot[0];
-  t += grow(b.dk, nd * 8) + grow(b.hk, m * 8);
+  t += grow(b.dk, nd * 8) + grow(b.hk, m * 8) + grow(b.hoff, (n + 1) * 8);
   if (b.cap_nc == 0) t += (1ULL << 20) * 8 + (1ULL << 24) * 4;  // new-clique lists
   if (st->cap_cc == 0) t += (1ULL << 20) * 16 + (1ULL << 24) * 4 + (1ULL << 20) * 24;  // candidates and dedup
   // the search's tables (queue, donation pool, handoff arena) on the first batch
@@ -1398,7 +1460,7 @@ void release_state(imce_state* st) {
                     &st->chash3, &st->cid2, &st->uniq, &st->sctl, &st->sdefer, &st->sbig};
   for (DevBuf* b : bufs) b->release();
   for (BatchSlot& b : st->slot)
-    for (DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.del_off, &b.del_vert}) d->release();
+    for (DevBuf* d : {&b.new_off, &b.new_vert, &b.dk, &b.hk, &b.hoff, &b.del_off, &b.del_vert}) d->release();
   st->ew.release();
   for (void** t : {&st->scan_tmp, &st->sort_tmp, &st->sort_tmp_b})
     if (*t) (void)hipFree(*t);
