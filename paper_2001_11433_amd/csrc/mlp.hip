@@ -14,6 +14,8 @@
 #include "dev.h"
 #include "internal.h"
 
+#include <mutex>
+
 namespace mce {
 
 namespace {
@@ -71,11 +73,15 @@ __global__ void __launch_bounds__(64) k_forward(const float* __restrict__ prm, c
 }
 
 // Gradient of L = (1/n) sum (yhat - t)^2 with respect to the first kMu
-// parameters, accumulated into grad (zeroed by the caller); loss[0] += L.
+// parameters: block b writes its samples' share to row b of `part` (kRow
+// floats: the kMu gradient entries, then its share of L); k_grad_reduce adds
+// the rows in block order, so the result does not depend on scheduling.
 // One wave per block; lanes are samples in the forward/backward sweep and
 // hidden units in the weight-gradient sweep.
+constexpr int kRow = kMu + 1;
+
 __global__ void __launch_bounds__(64) k_backward(const float* __restrict__ prm, const float* __restrict__ x,
-                                                 const float* __restrict__ t, uint64_t n, float* grad, float* loss) {
+                                                 const float* __restrict__ t, uint64_t n, float* part) {
   __shared__ float P[kTotal];
   __shared__ float H1[H][65];   // [unit][sample]
   __shared__ float H2[H][65];
@@ -143,15 +149,35 @@ __global__ void __launch_bounds__(64) k_backward(const float* __restrict__ prm, 
     __syncthreads();
   }
   const int u = lane;
-  for (int i = 0; i < H; ++i) atomicAdd(&grad[kW2 + u * H + i], gW2[i]);
-  for (int k = 0; k < 4; ++k) atomicAdd(&grad[kW1 + u * 4 + k], gW1[k]);
-  atomicAdd(&grad[kB1 + u], gb1);
-  atomicAdd(&grad[kB2 + u], gb2);
-  atomicAdd(&grad[kW3 + u], gw3);
-  if (lane == 0) atomicAdd(&grad[kB3], gb3);
+  float* row = part + (uint64_t)blockIdx.x * kRow;
+  for (int i = 0; i < H; ++i) row[kW2 + u * H + i] = gW2[i];
+  for (int k = 0; k < 4; ++k) row[kW1 + u * 4 + k] = gW1[k];
+  row[kB1 + u] = gb1;
+  row[kB2 + u] = gb2;
+  row[kW3 + u] = gw3;
+  if (lane == 0) row[kB3] = gb3;
   for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
-  if (lane == 0) atomicAdd(loss, l);
+  if (lane == 0) row[kMu] = l;
 }
+
+// grad[i] = sum over blocks b (in order) of part[b][i] for the trainable
+// parameters, 0 for mu/sigma; loss[0] = sum of the blocks' loss shares.
+__global__ void k_grad_reduce(const float* __restrict__ part, uint32_t nb, float* grad, float* loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > kTotal) return;
+  const int col = i < kMu ? i : kMu;
+  float a = 0.0f;
+  if (i < kMu || i == kTotal)
+    for (uint32_t b = 0; b < nb; ++b) a += part[(uint64_t)b * kRow + col];
+  if (i < kTotal)
+    grad[i] = i < kMu ? a : 0.0f;
+  else
+    loss[0] = a;
+}
+
+// per-device rows of the blocks' partial gradients
+std::mutex g_part_mu;
+DevBuf g_part[64];
 
 // Adam (Kingma & Ba) on the trainable parameters; step >= 1.
 __global__ void k_adam(float* prm, float* m, float* v, const float* grad, float lr, float b1, float b2, float eps,
@@ -265,13 +291,22 @@ int mce_mlp_grad(const float* params, const float* feat, const float* target, ui
     return MCE_EINVAL;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  MCE_TRY_HIP(hipMemsetAsync(grad, 0, kTotal * sizeof(float), s));
-  MCE_TRY_HIP(hipMemsetAsync(loss, 0, sizeof(float), s));
+  int dev = 0;
+  MCE_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    set_error("device index %d out of range", dev);
+    return MCE_ENOTSUP;
+  }
+  const uint32_t nb = n ? (grid_for(n) < 1024 ? grid_for(n) : 1024) : 0;
+  std::lock_guard<std::mutex> lk(g_part_mu);
+  DevBuf& part = g_part[dev];
+  MCE_TRY(part.ensure((uint64_t)std::max<uint32_t>(nb, 1) * kRow * sizeof(float)));
   if (n) {
-    hipLaunchKernelGGL(k_backward, dim3(grid_for(n) < 1024 ? grid_for(n) : 1024), dim3(64), 0, s, params, feat, target,
-                       n, grad, loss);
+    hipLaunchKernelGGL(k_backward, dim3(nb), dim3(64), 0, s, params, feat, target, n, part.as<float>());
     MCE_TRY_HIP(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kTotal + 1 + 255) / 256), dim3(256), 0, s, part.as<float>(), nb, grad, loss);
+  MCE_TRY_HIP(hipGetLastError());
   MCE_TRY_HIP(hipStreamSynchronize(s));
   return MCE_OK;
 }

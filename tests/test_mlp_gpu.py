@@ -110,6 +110,22 @@ def test_gradient_matches_reference(cm):
         assert abs(loss - R.loss(p.astype(np.float64), X, t)) <= 1e-5 * abs(loss)
 
 
+def test_gradient_is_reproducible(cm):
+    # the blocks' partial gradients are added in a fixed order: the same
+    # inputs give the same bits every time (and so does a whole training run)
+    p, X, t = _case(7, 70_000)
+    model = cm.CostModel(params=p)
+    g1, l1 = model.grad(_dev(X), _dev(t))
+    g1 = g1.cpu().numpy().copy()
+    for _ in range(3):
+        g2, l2 = model.grad(_dev(X), _dev(t))
+        assert np.array_equal(g1.view(np.uint32), g2.cpu().numpy().view(np.uint32)) and l1 == l2
+    a, b = cm.CostModel(params=p), cm.CostModel(params=p)
+    la = a.train(_dev(X), _dev(t), epochs=20)
+    lb = b.train(_dev(X), _dev(t), epochs=20)
+    assert la == lb and np.array_equal(a.numpy().view(np.uint32), b.numpy().view(np.uint32))
+
+
 def test_adam_step_matches_reference(cm):
     p, X, t = _case(4, 800)
     model = cm.CostModel(params=p)
