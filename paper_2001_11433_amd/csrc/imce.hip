@@ -363,6 +363,8 @@ constexpr uint32_t kStageN = 32, kStageV = 512;
 template <uint32_t MAXS, uint32_t MAXP>
 struct SubLds {
   uint32_t c[kSubMaxK];
+  uint64_t rb[kSubMaxK], re[kSubMaxK];  // row range of c[j] in the graph without H
+  uint32_t ord[kSubMaxK];               // members by ascending degree (ties by index)
   uint64_t pairs[MAXP];
   uint64_t S[2][MAXS];
   uint32_t np, ns;
@@ -446,6 +448,22 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
     if (lane < (int)k) L.c[lane] = nvert[b0 + lane];
     if (lane == 0) L.np = 0;
     __syncthreads();
+    // the members' rows, loaded once for all the subset tests below, and the
+    // members in ascending degree (the order in which a candidate extension is
+    // checked: shorter searches, and a non-neighbour found sooner)
+    {
+      const uint32_t x = lane < (int)k ? L.c[lane] : 0;
+      const uint64_t b = lane < (int)k ? rp[x] : 0, e = lane < (int)k ? rp[x + 1] : 0;
+      if (lane < (int)k) {
+        L.rb[lane] = b;
+        L.re[lane] = e;
+      }
+      const uint64_t key = lane < (int)k ? (((e - b) << 7) | (uint64_t)lane) : ~0ULL;
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < k; ++j) rank += readlane64(key, j) < key ? 1u : 0u;
+      if (lane < (int)k) L.ord[rank] = (uint32_t)lane;
+    }
+    __syncthreads();
     // batch edges inside c: lane j walks the new neighbours of c[j]
     if (lane < (int)k) {
       const uint32_t x = L.c[lane];
@@ -522,21 +540,17 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
       bool dup = false;
       for (uint32_t j = lane; j < i && !dup; j += kWave) dup = L.S[cur][j] == sm;
       if (ballot(dup)) continue;
-      // the member of c' with the smallest degree in G
+      // the member of c' with the smallest degree in G (the first in degree order)
       const bool mem = lane < (int)k && ((sm >> lane) & 1ULL);
       const uint32_t x = mem ? L.c[lane] : 0;
-      const uint64_t dx = mem ? rp[x + 1] - rp[x] : ~0ULL;
-      const uint64_t key = mem ? ((dx << 7) | (uint64_t)lane) : ~0ULL;
-      uint64_t mn = key;
-      for (int o = 32; o >= 1; o >>= 1) {
-        uint64_t t = __shfl_xor(mn, o, kWave);
-        mn = t < mn ? t : mn;
-      }
-      const int la = (int)(mn & 127);
-      const uint32_t a = L.c[la];
-      // is some w outside c' adjacent in G to every vertex of c'?
+      uint32_t first = 0;
+      while (first < k && !((sm >> L.ord[first]) & 1ULL)) ++first;
+      if (first >= k) continue;  // an empty subset (cannot occur: a split keeps one end of each pair)
+      const int la = (int)L.ord[first];
+      // is some w outside c' adjacent in G to every vertex of c'?  Each lane
+      // takes a neighbour w of c'[la] and checks the other members in degree order
       bool extends = false;
-      const uint64_t ab = rp[a], ae = rp[a + 1];
+      const uint64_t ab = L.rb[la], ae = L.re[la];
       for (uint64_t j0 = ab; j0 < ae; j0 += kWave) {
         const uint64_t j = j0 + lane;
         bool ok = j < ae;
@@ -545,12 +559,10 @@ __global__ void __launch_bounds__(64) k_subsumed(uint64_t nnew, const uint32_t* 
           const int64_t pos = bsearch_u32(L.c, k, w);
           if (pos >= 0 && ((sm >> pos) & 1ULL)) ok = false;
         }
-        uint64_t rest = sm & ~(1ULL << la);
-        while (ok && rest) {
-          const int y = __builtin_ctzll(rest);
-          rest &= rest - 1;
-          const uint32_t yy = L.c[y];
-          ok = bsearch_u32(col + rp[yy], rp[yy + 1] - rp[yy], w) >= 0;
+        for (uint32_t t = first + 1; ok && t < k; ++t) {
+          const uint32_t y = L.ord[t];
+          if (!((sm >> y) & 1ULL)) continue;
+          ok = bsearch_u32(col + L.rb[y], L.re[y] - L.rb[y], w) >= 0;
         }
         if (ballot(ok)) {
           extends = true;
