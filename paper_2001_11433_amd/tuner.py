@@ -170,6 +170,7 @@ IMCE_SPACE = (
     ("donate_interval", (16, 64, 256, 1024)),
     ("compact", ("inline", 4, 8, 20, 28)),
     ("waves_per_cu", (1, 2, 4, 8)),
+    ("compact_order", (0, 1, 2)),
 )
 
 
