@@ -334,3 +334,18 @@ def test_lds_row_cache_in_the_incremental_step(m):
     got = serving.run_alone(g, stream, lds_row_words=2048)
     for a, b in zip(ref, got):
         assert [a[k] for k in serving.RESULT_KEYS] == [b[k] for k in serving.RESULT_KEYS]
+
+
+def test_handoff_budget_overflow_is_searched_in_place(m):
+    # a tiny handoff budget (1 MiB): the nodes past it are searched in place by
+    # the first kernel; results, node counts and per-subproblem triples are
+    # those of the default budget, for static and exclusion-mode searches
+    g = gg.plant_communities(gg.chung_lu(200_000, 2.1, 16, seed=21), count=80, smin=30, smax=60, p=0.85, seed=22)
+    want = m.mce_static(g, rank="degree", per_vertex=True)
+    got = m.mce_static(g, rank="degree", per_vertex=True, hand_mb=1)
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == (want["count"], want["set_hash"], want["nodes_total"])
+    for k in ("nodes_v", "count_v", "hash_v"):
+        assert bool((got[k] == want[k]).all()), k
+    assert got["handed"] < want["handed"]
+    ref = O.mce_parmce(g, "degree", threads=8)
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == (ref.count, ref.set_hash, ref.nodes)
