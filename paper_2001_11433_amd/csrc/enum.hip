@@ -608,9 +608,13 @@ __device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compac
         if (cliqm) {
           T.tc += (uint32_t)__popcll(cliqm);
           const uint64_t zw = grandm ? bpermute64(c.zP, w) : 0ULL;
+          // clique_term(zsum + z(q) [+ z(w)], |K| + 1 [+ 1]) with the sums over K
+          // and the size term formed once, in scalar registers
+          const uint64_t b1 = zsum + (uint64_t)(kl + 1) * kGolden;
+          const uint64_t b2 = b1 + kGolden;
           if ((cliqm >> lane) & 1ULL) {
             const bool two = (grandm >> lane) & 1ULL;
-            T.vh += clique_term(zsum + c.zP + (two ? zw : 0ULL), kl + (two ? 2u : 1u));
+            T.vh += mix64((two ? b2 + zw : b1) + c.zP);
           }
           if (a.emit_extra) {
             uint64_t cm = cliqm;
