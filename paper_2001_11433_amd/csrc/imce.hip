@@ -1159,7 +1159,7 @@ int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t r
 int phase_b(imce_state* st, int si, hipStream_t s) {
   BatchSlot& b = st->slot[si];
   if (b.m == 0) return MCE_OK;
-  const uint64_t n = st->n, m = b.m, nd = b.nd, nc_new = b.nc_new;
+  const uint64_t n = st->n, m = b.m, nc_new = b.nc_new;
   const int mb = b.remove ? b.next : b.prev;  // the graph without H
   const uint64_t* mrp = st->rp[mb].as<uint64_t>();
   const uint32_t* mcol = st->col[mb].as<uint32_t>();
