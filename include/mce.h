@@ -217,8 +217,8 @@ typedef struct {
 
 /* All maximal cliques of `g` (Algorithm 4 over Algorithm 1).
  * opts may be NULL (defaults), cliques and per_vertex may be NULL.
- * Supported envelope: n < 2^32, |cand| of every subproblem <= 4096 (else
- * MCE_ENOTSUP; cliques up to 4097 vertices are then found), and for
+ * Supported envelope: n < 2^32, |cand| of every subproblem <= 8192 (else
+ * MCE_ENOTSUP; cliques up to 8193 vertices are then found), and for
  * materialised output n_verts < 2^32. */
 int mce_static(const mce_csr* g, mce_rank rank, const mce_opts* opts, mce_result* out,
                mce_clique_buf* cliques, const mce_per_vertex* per_vertex);

@@ -93,7 +93,7 @@ __device__ __forceinline__ void stat_add(uint64_t& f, uint64_t v) {
 }
 
 struct Lds {
-  uint64_t sP[64];
+  uint64_t sP[kMaxCand / 64];
   uint64_t cstk[kCFrames * kCF];
   uint32_t kG[kKLds];  // ids of K, roots first
   uint32_t xl[64];     // wide rows of the fini vertices kept by a re-base
@@ -148,7 +148,7 @@ struct Compact {
 // scope invalidates the whole L2 of the XCD, which idle waves must not do
 // while others compute.  One acquire fence follows a successful claim, so the
 // task record written before the slot was published is visible.
-__device__ uint64_t claim_task(const EnumArgs& a) {
+__device__ __forceinline__ uint64_t claim_task(const EnumArgs& a) {
   uint64_t idx = fetch_add(&a.ctl[CTL_HEAD], 1);
   if (idx >= a.qcap) return 0;
   // back off while waiting: idle waves must not crowd the memory channel of
@@ -232,7 +232,7 @@ __device__ uint32_t pool_pop(const EnumArgs& a) {
 }
 
 // Returns a block whose contents the caller has finished reading.
-__device__ void pool_push(const EnumArgs& a, uint32_t idx) {
+__device__ __forceinline__ void pool_push(const EnumArgs& a, uint32_t idx) {
   for (;;) {
     uint64_t old = ld_relaxed(&a.ctl[CTL_FREE]);
     __hip_atomic_store(&a.pool_next[idx], (uint32_t)old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -285,30 +285,86 @@ struct WideCtx {
   uint32_t F, wp, base, top, s, kroot;
 };
 
+// A wide node's per-lane masks (cand, fini from cand, unvisited ext, excluded
+// branches) hold NW 64-bit words to a lane: word j lives in lane j % 64 of
+// register j / 64, so a subproblem may have 64 * NW words of candidates.
+// Word j (wave-uniform) of such a mask:
+template <int NW>
+__device__ __forceinline__ uint64_t word_of(const uint64_t (&v)[NW], uint32_t j) {
+  if constexpr (NW == 1) {
+    return readlane64(v[0], (int)j);
+  } else {
+    const uint64_t lo = readlane64(v[0], (int)(j & 63));
+    const uint64_t hi = readlane64(v[1], (int)(j & 63));
+    return (j >> 6) ? hi : lo;
+  }
+}
+
+// Some word of the mask is non-zero.
+template <int NW>
+__device__ __forceinline__ bool any_word(const uint64_t (&v)[NW]) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) o |= v[i];
+  return ballot(o != 0) != 0;
+}
+
+// Rank of each lane's first set bit among all set bits of a mask, in word
+// order: cc[i] = this lane's bits in register i, before[i] = set bits in the
+// words below word lane + 64 i; returns the total.
+template <int NW>
+__device__ __forceinline__ uint32_t word_ranks(const uint64_t (&v)[NW], uint32_t wp, uint32_t (&cc)[NW],
+                                               uint32_t (&before)[NW]) {
+  const int lane = lane_id();
+  uint32_t total = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    cc[i] = (uint32_t)lane + 64u * i < wp ? (uint32_t)__popcll(v[i]) : 0u;
+    const uint32_t incl = wave_incl_scan_u32(cc[i]);
+    before[i] = total + incl - cc[i];
+    total += readlane32(incl, 63);
+  }
+  return total;
+}
+
+// The lowest r bits of x.
+__device__ __forceinline__ uint64_t low_bits(uint64_t x, uint32_t r) {
+  uint64_t lo = 0;
+  for (uint32_t z = 0; z < r; ++z) {
+    lo |= x & (~x + 1);
+    x &= x - 1;
+  }
+  return lo;
+}
+
 // Hands the second half of the shallowest wide frame's unvisited children to
 // an idle wave.  Returns true if a record was queued.
-__device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& can_donate) {
+template <int NW>
+__device__ bool donate_wide_n(const EnumArgs& a, const WideCtx& w, bool& can_donate) {
   const int lane = lane_id();
   const uint32_t O_XP = w.wp, O_EXT = 2 * w.wp;
   uint32_t i = w.base;
-  uint64_t e = 0;
+  uint64_t e[NW];
   for (; i < w.top; ++i) {
-    e = lane < (int)w.wp ? w.stk[(uint64_t)i * w.F + O_EXT + lane] : 0;
-    if (ballot(e != 0)) break;
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+      const uint32_t j = (uint32_t)lane + 64u * r;
+      e[r] = j < w.wp ? w.stk[(uint64_t)i * w.F + O_EXT + j] : 0;
+    }
+    if (any_word(e)) break;
   }
   if (i >= w.top) return false;
   const uint32_t klen = w.kroot + i;
   const uint64_t size = R_HDR + w.F + (klen + 1) / 2;
   if (size > kBlockWords) return false;
-  const uint32_t cc = (uint32_t)__popcll(e);
-  const uint32_t incl = wave_incl_scan_u32(cc);
-  const uint32_t total = readlane32(incl, 63);
-  const uint32_t keep = total / 2;
-  const uint32_t before = incl - cc;
-  const uint32_t r = keep > before ? (keep - before < cc ? keep - before : cc) : 0;
-  uint64_t rest = e;
-  for (uint32_t z = 0; z < r; ++z) rest &= rest - 1;
-  const uint64_t km = e & ~rest;  // kept: the lowest `keep` children
+  uint32_t cc[NW], before[NW];
+  const uint32_t keep = word_ranks(e, w.wp, cc, before) / 2;
+  uint64_t km[NW];  // kept: the lowest `keep` children
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    const uint32_t n = keep > before[r] ? (keep - before[r] < cc[r] ? keep - before[r] : cc[r]) : 0u;
+    km[r] = low_bits(e[r], n);
+  }
   const uint32_t blk = reserve_record(a, can_donate);
   if (blk == kNil) return false;
   uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
@@ -320,19 +376,32 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
     rec[R_DEPTH] = i;
     rec[R_KLEN] = klen;
   }
-  // lane j owns word j of P, Xp and ext: P minus the kept children, Xp plus
-  // them, ext = the donated children
-  if (lane < (int)w.wp) {
-    rec[R_HDR + lane] = fi[lane] & ~km;
-    rec[R_HDR + O_XP + lane] = fi[O_XP + lane] | km;
-    rec[R_HDR + O_EXT + lane] = rest;
+  // word j of P, Xp and ext: P minus the kept children, Xp plus them, ext =
+  // the donated children
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    const uint32_t j = (uint32_t)lane + 64u * r;
+    if (j < w.wp) {
+      rec[R_HDR + j] = fi[j] & ~km[r];
+      rec[R_HDR + O_XP + j] = fi[O_XP + j] | km[r];
+      rec[R_HDR + O_EXT + j] = e[r] & ~km[r];
+    }
   }
   for (uint32_t k = 3 * w.wp + lane; k < w.F; k += kWave) rec[R_HDR + k] = fi[k];
   for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + R_HDR + w.F))[j] = w.kG[j];
-  if (lane < (int)w.wp) w.stk[(uint64_t)i * w.F + O_EXT + lane] = km;
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    const uint32_t j = (uint32_t)lane + 64u * r;
+    if (j < w.wp) w.stk[(uint64_t)i * w.F + O_EXT + j] = km[r];
+  }
   publish_record(a, blk);
   __threadfence_block();
   return true;
+}
+
+__device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& can_donate) {
+  (void)L;
+  return w.wp > 64 ? donate_wide_n<2>(a, w, can_donate) : donate_wide_n<1>(a, w, can_donate);
 }
 
 // Deals a root's children out at launch (mce_opts.split): `k` chunks of
@@ -341,36 +410,42 @@ __device__ bool donate_wide(const EnumArgs& a, Lds& L, const WideCtx& w, bool& c
 // the rest here.  Each chunk is a continuation of the root whose cand lacks
 // the earlier children and whose fini holds them (Algorithm 3's child
 // formula), so the recursion tree is unchanged.  `fr` is the root frame with
-// its fini words already in place; returns this lane's word of the kept ext.
-template <bool EXCL>
-__device__ uint64_t split_root(const EnumArgs& a, const uint32_t* kG, uint64_t* fr, uint32_t F, uint32_t wp, uint32_t s,
-                               uint32_t kroot, uint64_t rP, uint64_t rXp, uint64_t rExt, uint64_t rF, uint64_t zsum,
-                               uint32_t k, bool& can_donate) {
+// its fini words already in place; rExt is left holding the kept children.
+template <bool EXCL, int NW>
+__device__ void split_root(const EnumArgs& a, const uint32_t* kG, uint64_t* fr, uint32_t F, uint32_t wp, uint32_t s,
+                           uint32_t kroot, const uint64_t (&rP)[NW], const uint64_t (&rXp)[NW], uint64_t (&rExt)[NW],
+                           const uint64_t (&rF)[NW], uint64_t zsum, uint32_t k, bool& can_donate) {
   const int lane = lane_id();
   const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp;
-  const uint32_t cc = lane < (int)wp ? (uint32_t)__popcll(rExt) : 0u;
-  const uint32_t incl = wave_incl_scan_u32(cc);
-  const uint32_t total = readlane32(incl, 63);
+  uint32_t cc[NW], before[NW];
+  const uint32_t total = word_ranks(rExt, wp, cc, before);
   const uint32_t chunks = k < total ? k : total;
-  if (chunks < 2 || R_HDR + F + (kroot + 1) / 2 > kBlockWords) return rExt;
+  if (chunks < 2 || R_HDR + F + (kroot + 1) / 2 > kBlockWords) return;
   const uint32_t size = (total + chunks - 1) / chunks;
-  const uint32_t before = incl - cc;
-  if (EXCL && lane < (int)wp) fr[O_FB + lane] = rF;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint32_t j = (uint32_t)lane + 64u * i;
+    if (EXCL && j < wp) fr[O_FB + j] = rF[i];
+  }
   if (lane == 0) fr[F - 1] = zsum;
   __threadfence_block();
-  uint64_t keep = rExt;
-  for (uint32_t j = chunks - 1; j >= 1 && can_donate; --j) {
-    const uint32_t lo = j * size;  // rank of the chunk's first child
+  uint64_t keep[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) keep[i] = rExt[i];
+  for (uint32_t c = chunks - 1; c >= 1 && can_donate; --c) {
+    const uint32_t lo = c * size;  // rank of the chunk's first child
     if (lo >= total) continue;
     // this lane's children of rank < lo
-    const uint32_t r = lo > before ? (lo - before < cc ? lo - before : cc) : 0u;
-    uint64_t below = 0, m = rExt;
-    for (uint32_t z = 0; z < r; ++z) {
-      below |= m & (~m + 1);
-      m &= m - 1;
+    uint64_t below[NW], chunk[NW];
+    uint64_t any = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t r = lo > before[i] ? (lo - before[i] < cc[i] ? lo - before[i] : cc[i]) : 0u;
+      below[i] = low_bits(rExt[i], r);
+      chunk[i] = keep[i] & ~below[i];
+      any |= chunk[i];
     }
-    const uint64_t chunk = keep & ~below;
-    if (ballot(chunk != 0) == 0) continue;
+    if (ballot(any != 0) == 0) continue;
     const uint32_t blk = reserve_record(a, can_donate);
     if (blk == kNil) break;
     uint64_t* rec = a.pool + (uint64_t)blk * kBlockWords;
@@ -380,17 +455,23 @@ __device__ uint64_t split_root(const EnumArgs& a, const uint32_t* kG, uint64_t* 
       rec[R_DEPTH] = 0;
       rec[R_KLEN] = kroot;
     }
-    if (lane < (int)wp) {
-      rec[R_HDR + lane] = rP & ~below;
-      rec[R_HDR + O_XP + lane] = rXp | below;
-      rec[R_HDR + O_EXT + lane] = chunk;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t j = (uint32_t)lane + 64u * i;
+      if (j < wp) {
+        rec[R_HDR + j] = rP[i] & ~below[i];
+        rec[R_HDR + O_XP + j] = rXp[i] | below[i];
+        rec[R_HDR + O_EXT + j] = chunk[i];
+      }
     }
     for (uint32_t q = 3 * wp + lane; q < F; q += kWave) rec[R_HDR + q] = fr[q];
     for (uint32_t q = lane; q < kroot; q += kWave) ((uint32_t*)(rec + R_HDR + F))[q] = kG[q];
     publish_record(a, blk);
-    keep &= below;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) keep[i] &= below[i];
   }
-  return keep;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) rExt[i] = keep[i];
 }
 
 // K is maximal: count it, hash it, and optionally write it out.
@@ -529,7 +610,7 @@ __device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
 // Entry: expand = true starts at the node (P, Xp, Xx) itself; expand = false
 // resumes a node whose deep children D are left (a donated record).
 template <bool EXCL, bool BIGK, class LT>
-__device__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
+__device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
                             uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t D, uint64_t F, uint64_t zsum,
                             bool expand, uint32_t kbase, uint32_t wv, bool& can_donate, uint32_t& since,
                             const WideCtx* wide, Diag& dg) {
@@ -764,7 +845,7 @@ __device__ void compact_keys(Compact& c) {
 }
 
 template <bool EXCL>
-__device__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* kG, uint64_t& P, uint64_t& Xp,
+__device__ __forceinline__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* kG, uint64_t& P, uint64_t& Xp,
                                     uint64_t& Xx, uint64_t& ext, uint64_t& D, uint64_t& zsum, uint64_t& F,
                                     uint32_t& klen) {
   const int lane = lane_id();
@@ -804,15 +885,15 @@ __device__ __forceinline__ uint32_t hand_words(uint32_t wp, uint32_t nx, uint32_
 }
 
 // Re-bases a wide node onto the compact 64 + 64 universe: gathers the rows of
-// its candidates (the set bits of the wide mask rP, lane k holding word k, in
+// its candidates (the set bits of the wide mask rP, NW words to a lane, in
 // ascending order) and of its kept fini vertices (local row ux, lane < nx)
 // from the subproblem's bit rows.  Sets c (rows, ids, np, nx), the fini ids
 // gX (lane < nx) and, with exclusion, the compact mask of candidates whose
-// branch is excluded (from the wide mask rF, lane k holding word k).
-template <bool EXCL>
+// branch is excluded (from the wide mask rF, laid out like rP).
+template <bool EXCL, int NW>
 __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const uint32_t* gid, uint64_t nrow,
-                               uint32_t wp, uint64_t rP, uint64_t rF, uint32_t ux, uint32_t np, uint32_t nx,
-                               Compact& c, uint32_t& gX, uint64_t& Fc) {
+                               uint32_t wp, const uint64_t (&rP)[NW], const uint64_t (&rF)[NW], uint32_t ux,
+                               uint32_t np, uint32_t nx, Compact& c, uint32_t& gX, uint64_t& Fc) {
   const int lane = lane_id();
   c.np = np;
   c.nx = nx;
@@ -820,7 +901,7 @@ __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const
   {
     uint32_t j = 0;
     for (uint32_t k = 0; k < wp; ++k) {
-      uint64_t m = readlane64(rP, k);
+      uint64_t m = word_of(rP, k);
       while (m) {
         const uint32_t b = (uint32_t)__builtin_ctzll(m);
         if (lane == (int)j) pm = k * 64 + b;
@@ -832,12 +913,12 @@ __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const
   uint64_t cPP = 0, cXP = 0, cEx = 0, cF = 0;
   uint32_t cnt = 0;
   for (uint32_t k = 0; k < wp; ++k) {
-    uint64_t m = readlane64(rP, k);
+    uint64_t m = word_of(rP, k);
     if (m == 0) continue;
     const uint64_t wP = lane < (int)np ? rowP[(uint64_t)k * nrow + pm] : 0;
     const uint64_t wX = lane < (int)nx ? rowP[(uint64_t)k * nrow + ux] : 0;
     const uint64_t wE = (EXCL && lane < (int)np) ? excl[(uint64_t)pm * wp + k] : 0;
-    const uint64_t fk = EXCL ? readlane64(rF, k) : 0;
+    const uint64_t fk = EXCL ? word_of(rF, k) : 0;
     while (m) {
       const uint32_t b = (uint32_t)__builtin_ctzll(m);
       cPP |= ((wP >> b) & 1ULL) << cnt;
@@ -921,23 +1002,379 @@ __device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compac
   const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
   const uint64_t* excl = rowG + (uint64_t)wp * nrow + (uint64_t)p * wx;
   const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
+  // records come only from subproblems of at most 64 cand words
   const uint64_t* w = rec + 4;
-  const uint64_t rP = lane < (int)wp ? w[lane] : 0;
+  const uint64_t rP[1] = {lane < (int)wp ? w[lane] : 0};
   w += wp;
-  uint64_t rF = 0;
+  uint64_t rF[1] = {0};
   if (EXCL) {
-    rF = lane < (int)wp ? w[lane] : 0;
+    rF[0] = lane < (int)wp ? w[lane] : 0;
     w += wp;
   }
   const uint32_t* u = (const uint32_t*)w;
   const uint32_t ux = lane < (int)nx ? u[lane] : 0;
   for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[nx + j];
   uint32_t gX;
-  compact_gather<EXCL>(rowG, excl, gid, nrow, wp, rP, rF, ux, np, nx, c, gX, F);
+  compact_gather<EXCL, 1>(rowG, excl, gid, nrow, wp, rP, rF, ux, np, nx, c, gX, F);
   c.keyX = gX;
   compact_keys(c);
   P = np == 64 ? ~0ULL : ((1ULL << np) - 1);
   Xx = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
+}
+
+// One wide task: a subproblem's root or a donated wide continuation, searched
+// with its node masks NW words to a lane (word j in lane j % 64 of register
+// j / 64).  Descends until a node's cand fits the compact universe, then
+// re-bases it (searched here, or handed to the compact kernel when NW is 1).
+template <bool EXCL, int NW>
+__device__ __forceinline__ void wide_task(const EnumArgs& a, Lds& L, uint64_t* lds_stack, uint64_t* gstk,
+                                          uint32_t* gK, bool cont, uint32_t blk, const uint64_t* rec, uint32_t s,
+                                          uint32_t ksplit, uint32_t p, uint32_t x, uint32_t wv, bool bigk,
+                                          uint32_t* kG, uint32_t kcap, Acc& acc, bool& overflow, bool& can_donate,
+                                          uint32_t& since, Diag& dg) {
+  const int lane = lane_id();
+  const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
+  const uint32_t F = 3 * wp + wf + wx + 1;
+  const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp, O_XX = 3 * wp + wf, O_Z = O_XX + wx;
+  const uint64_t nrow = (uint64_t)p + x;
+  const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
+  const uint64_t* rowPX = rowG + (uint64_t)wp * nrow;
+  const uint64_t* excl = rowPX + (uint64_t)p * wx;
+  const uint64_t* F0 = excl + (uint64_t)p * wp;
+  const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
+  const uint32_t kroot = EXCL ? 2 : 1;
+  // width class: rows over the cand columns that fit the wave's LDS row
+  // cache are read from LDS for the whole task, wider ones from the arena
+  const uint64_t rwords = (uint64_t)wp * nrow;
+  const uint64_t* rowP = rowG;
+  if (rwords <= a.lds_rows && (p > 64 || x > 64)) {
+    uint64_t* cache = lds_stack + kLdsWords;
+    for (uint64_t k = lane; k < rwords; k += kWave) cache[k] = rowG[k];
+    __syncthreads();
+    rowP = cache;
+  }
+
+  uint64_t* stk;
+  uint32_t cap;
+  if ((uint64_t)(p + 2) * F <= kLdsWords) {
+    stk = lds_stack;
+    cap = kLdsWords / F;
+  } else {
+    stk = gstk;
+    cap = (uint32_t)(a.stack_words / F);
+  }
+  const uint32_t base = cont ? (uint32_t)readlane64(rec[R_DEPTH], 0) : 0u;
+  overflow = base + 2 > cap || base + kroot >= kcap;
+
+  uint64_t rP[NW], rXp[NW], rExt[NW], rF[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) rP[i] = rXp[i] = rExt[i] = rF[i] = 0;
+  uint64_t zsum = 0;
+  uint32_t d = base;
+  uint64_t* fr = stk + (uint64_t)d * F;
+  bool expand = false;
+  if (!overflow) {
+    if (!cont) {
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t j = (uint32_t)lane + 64u * i;
+        if (j < wp) {
+          rP[i] = full_word(p, j);
+          if (EXCL) rF[i] = F0[j];
+        }
+      }
+      for (uint32_t k = lane; k < wx; k += kWave) fr[O_XX + k] = full_word(x, k);
+      const uint32_t r0 = readlane32(a.sub.r0[s], 0);
+      zsum = mix64(r0);
+      if (lane == 0) kG[0] = r0;
+      if (EXCL) {
+        const uint32_t r1 = readlane32(a.sub.r1[s], 0);
+        zsum += mix64(r1);
+        if (lane == 0) kG[1] = r1;
+      }
+      expand = true;
+    } else {
+      const uint32_t klen = (uint32_t)readlane64(rec[R_KLEN], 0);
+      for (uint32_t k = lane; k < F; k += kWave) fr[k] = rec[R_HDR + k];
+      for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + R_HDR + F))[j];
+      __threadfence_block();
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t j = (uint32_t)lane + 64u * i;
+        if (j < wp) {
+          rP[i] = fr[j];
+          rXp[i] = fr[O_XP + j];
+          rExt[i] = fr[O_EXT + j];
+          if (EXCL) rF[i] = fr[O_FB + j];
+        }
+      }
+      zsum = readlane64(fr[O_Z], 0);
+    }
+  }
+  if (cont) {
+    __threadfence_block();
+    if (lane == 0) pool_push(a, blk);
+  }
+  WideCtx wctx;
+  wctx.stk = stk;
+  wctx.kG = kG;
+  wctx.F = F;
+  wctx.wp = wp;
+  wctx.base = base;
+  wctx.top = base;
+  wctx.s = s;
+  wctx.kroot = kroot;
+
+  while (!overflow) {
+    bool do_pop = false;
+    if (expand) {
+      expand = false;
+      if (!any_word(rP)) {
+        ++acc.tn;
+        // cand empty: K is maximal iff fini is empty too
+        bool xe = !any_word(rXp);
+        if (xe) {
+          bool nz = false;
+          for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
+          xe = ballot(nz) == 0;
+        }
+        if (xe) emit(a, acc, L.hist, zsum, kroot + d, kG);
+        do_pop = true;
+      } else {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t j = (uint32_t)lane + 64u * i;
+          if (j < wp) L.sP[j] = rP[i];
+        }
+        __syncthreads();
+        uint32_t p_cnt = 0;
+        for (uint32_t j = 0; j < wp; ++j) p_cnt += (uint32_t)__popcll(L.sP[j]);
+        // One pass over the rows of P u X: t_u for the pivot and, when
+        // |cand| <= 64, the fini vertices with a neighbour in cand (the
+        // vertices a re-based node keeps; give up beyond 64).
+        bool ok = p_cnt <= 64 && kroot + d + kCFrames <= kcap;
+        uint32_t nx = 0;
+        uint64_t best = 0;
+        uint32_t bu = 0;
+        uint32_t s_mem = 0;
+        // one 64-row chunk: member mask M, fini members MX, first row u0
+        auto chunk = [&](uint64_t M, uint64_t MX, uint32_t u0) {
+          s_mem += (uint32_t)__popcll(M);
+          const uint32_t u = u0 + lane;
+          uint32_t tu = 0;
+          if ((M >> lane) & 1ULL) {
+            for (uint32_t j = 0; j < wp; ++j) tu += (uint32_t)__popcll(L.sP[j] & rowP[(uint64_t)j * nrow + u]);
+            const uint64_t key = ((uint64_t)tu << 32) | (0xFFFFFFFFu - gid[u]);
+            if (key > best) {
+              best = key;
+              bu = u;
+            }
+          }
+          if (ok) {
+            const bool keepx = ((MX >> lane) & 1ULL) && tu > 0;
+            const uint64_t b = ballot(keepx);
+            const uint32_t cnt = (uint32_t)__popcll(b);
+            if (nx + cnt > 64) {
+              ok = false;
+            } else {
+              if (keepx) L.xl[nx + mask_prefix(b, lane)] = u;
+              nx += cnt;
+            }
+          }
+        };
+        uint64_t mem[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) mem[i] = rP[i] | rXp[i];
+        for (uint32_t k = 0; k < wp; ++k) {
+          const uint64_t M = word_of(mem, k);
+          if (M) chunk(M, word_of(rXp, k), k * 64);
+        }
+        // fini words of the root fini: loaded lane-parallel, only non-zero words visited
+        for (uint32_t kb = 0; kb < wx; kb += kWave) {
+          const uint64_t xw = kb + lane < wx ? fr[O_XX + kb + lane] : 0;
+          uint64_t nzm = ballot(xw != 0);
+          while (nzm) {
+            const uint32_t jj = (uint32_t)__builtin_ctzll(nzm);
+            nzm &= nzm - 1;
+            const uint64_t M = readlane64(xw, jj);
+            chunk(M, M, p + (kb + jj) * 64);
+          }
+        }
+        bool rebased = false;
+        if (ok) {
+          // re-base this node and search its subtree in compact form,
+          // here or (handed off) in the compact kernel
+          const uint64_t tr = now();
+          stat_add(dg.rebases, 1);
+          __syncthreads();
+          const uint32_t ux = lane < (int)nx ? L.xl[lane] : 0;
+          wctx.top = d;
+          bool handed = false;
+          if constexpr (NW == 1)
+            handed = a.hand && kroot + d <= kHandK &&
+                     hand_off<EXCL>(a, kG, s, wp, rP[0], rF[0], ux, p_cnt, nx, zsum, kroot + d);
+          if (handed) {
+            // a handed-off subtree is work done here as far as donation
+            // pacing goes, else the wide frames would rarely be offered
+            since += a.donate_interval / 16 + 1;
+            stat_add(dg.t_rebase, now() - tr);
+          } else {
+            Compact c;
+            uint32_t gX;
+            uint64_t Fc;
+            compact_gather<EXCL, NW>(rowP, excl, gid, nrow, wp, rP, rF, ux, p_cnt, nx, c, gX, Fc);
+            c.keyX = gX;
+            compact_keys(c);
+            const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
+            const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
+            stat_add(dg.t_rebase, now() - tr);
+            if (bigk)
+              compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, can_donate,
+                                      since, &wctx, dg);
+            else
+              compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv, can_donate,
+                                       since, &wctx, dg);
+          }
+          rebased = true;
+          do_pop = true;
+        }
+        if (!rebased) {
+          ++acc.tn;
+          // pivot: largest |P n Gamma(u)| over u in P u X, smallest id on ties
+          const uint64_t mx = wave_max_u64(best);
+          const int wl = __ffsll((unsigned long long)ballot(best == mx)) - 1;
+          const uint32_t piv = readlane32(bu, wl);
+          uint32_t ce = 0;
+#pragma unroll
+          for (int i = 0; i < NW; ++i) {
+            const uint32_t j = (uint32_t)lane + 64u * i;
+            rExt[i] = j < wp ? (rP[i] & ~rowP[(uint64_t)j * nrow + piv]) : 0;
+            ce += (uint32_t)__popcll(rExt[i]);
+          }
+          const uint64_t n_ext = wave_sum_u64((uint64_t)ce);
+          acc.ssum += s_mem;
+          acc.esum += n_ext;
+          if (ksplit > 1 && !cont && d == 0)
+            split_root<EXCL, NW>(a, kG, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
+        }
+        __syncthreads();
+      }
+    }
+    if (!do_pop) {
+      // the lowest unvisited child q: the first word with a set bit
+      uint32_t wq = kNone;
+      uint64_t w = 0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        if (wq == kNone) {
+          const uint64_t m = ballot(rExt[i] != 0);
+          if (m) {
+            const int kq = __ffsll((unsigned long long)m) - 1;
+            w = readlane64(rExt[i], kq);
+            wq = 64u * i + (uint32_t)kq;
+          }
+        }
+      }
+      if (wq == kNone) {
+        do_pop = true;
+      } else {
+        const int b = __ffsll((unsigned long long)w) - 1;
+        const uint32_t q = wq * 64 + b;
+        uint64_t qb[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          qb[i] = (uint32_t)lane + 64u * i == wq ? (1ULL << b) : 0;
+          rExt[i] &= ~qb[i];
+        }
+        if (EXCL && ((word_of(rF, wq) >> b) & 1ULL)) {
+          // K u {q} would contain an excluded edge: q moves to fini unvisited
+#pragma unroll
+          for (int i = 0; i < NW; ++i) {
+            rP[i] &= ~qb[i];
+            rXp[i] |= qb[i];
+          }
+          continue;
+        }
+        if (d + 2 > cap || kroot + d + 1 >= kcap) {
+          overflow = true;
+          break;
+        }
+        uint64_t cP[NW], cXp[NW], cF[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t j = (uint32_t)lane + 64u * i;
+          const uint64_t rq = j < wp ? rowP[(uint64_t)j * nrow + q] : 0;
+          cP[i] = rP[i] & rq;
+          cXp[i] = rXp[i] & rq;
+          rP[i] &= ~qb[i];
+          rXp[i] |= qb[i];
+        }
+        uint64_t* ch = fr + F;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t j = (uint32_t)lane + 64u * i;
+          if (j < wp) {
+            fr[j] = rP[i];
+            fr[O_XP + j] = rXp[i];
+            fr[O_EXT + j] = rExt[i];
+            if (EXCL) fr[O_FB + j] = rF[i];
+          }
+        }
+        for (uint32_t k = lane; k < wx; k += kWave) ch[O_XX + k] = fr[O_XX + k] & rowPX[(uint64_t)q * wx + k];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t j = (uint32_t)lane + 64u * i;
+          cF[i] = (EXCL && j < wp) ? (rF[i] | excl[(uint64_t)q * wp + j]) : 0;
+        }
+        const uint32_t gq = gid[q];
+        if (lane == 0) {
+          fr[O_Z] = zsum;
+          kG[kroot + d] = gq;
+        }
+        zsum += mix64(gq);
+        if (lane == 0) ch[O_Z] = zsum;
+        __threadfence_block();
+        fr = ch;
+        ++d;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          rP[i] = cP[i];
+          rXp[i] = cXp[i];
+          rF[i] = cF[i];
+          rExt[i] = 0;
+        }
+        expand = true;
+
+        // hand the second half of the shallowest unvisited siblings to idle waves
+        if (can_donate && ++since >= a.donate_interval) {
+          since = 0;
+          stat_add(dg.t_donate, 0 - now());
+          wctx.top = d;
+          if (starving(a)) {
+            stat_add(dg.attempts, 1);
+            donate_wide(a, L, wctx, can_donate);
+          }
+          stat_add(dg.t_donate, now());
+        }
+        continue;
+      }
+    }
+    // pop
+    if (d == base) break;
+    fr -= F;
+    --d;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t j = (uint32_t)lane + 64u * i;
+      if (j < wp) {
+        rP[i] = fr[j];
+        rXp[i] = fr[O_XP + j];
+        rExt[i] = fr[O_EXT + j];
+        if (EXCL) rF[i] = fr[O_FB + j];
+      }
+    }
+    zsum = readlane64(fr[O_Z], 0);
+  }
 }
 
 // --- the kernel ---------------------------------------------------------------
@@ -997,283 +1434,13 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
         compact_dfs<EXCL, false>(a, L, gK, c, s, P, Xp, Xx, ext, D, F, zsum, false, klen, wv, can_donate,
                                  since, nullptr, dg);
     } else {
-      const uint32_t wp = (p + 63) >> 6, wx = (x + 63) >> 6, wf = EXCL ? wp : 0;
-      const uint32_t F = 3 * wp + wf + wx + 1;
-      const uint32_t O_XP = wp, O_EXT = 2 * wp, O_FB = 3 * wp, O_XX = 3 * wp + wf, O_Z = O_XX + wx;
-      const uint64_t nrow = (uint64_t)p + x;
-      const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
-      const uint64_t* rowPX = rowG + (uint64_t)wp * nrow;
-      const uint64_t* excl = rowPX + (uint64_t)p * wx;
-      const uint64_t* F0 = excl + (uint64_t)p * wp;
-      const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
-      const uint32_t kroot = EXCL ? 2 : 1;
-      // width class: rows over the cand columns that fit the wave's LDS row
-      // cache are read from LDS for the whole task, wider ones from the arena
-      const uint64_t rwords = (uint64_t)wp * nrow;
-      const uint64_t* rowP = rowG;
-      if (rwords <= a.lds_rows && (p > 64 || x > 64)) {
-        uint64_t* cache = lds_stack + kLdsWords;
-        for (uint64_t k = lane; k < rwords; k += kWave) cache[k] = rowG[k];
-        __syncthreads();
-        rowP = cache;
-      }
-
-      uint64_t* stk;
-      uint32_t cap;
-      if ((uint64_t)(p + 2) * F <= kLdsWords) {
-        stk = lds_stack;
-        cap = kLdsWords / F;
-      } else {
-        stk = gstk;
-        cap = (uint32_t)(a.stack_words / F);
-      }
-      const uint32_t base = cont ? (uint32_t)readlane64(rec[R_DEPTH], 0) : 0u;
-      overflow = base + 2 > cap || base + kroot >= kcap;
-
-      uint64_t rP = 0, rXp = 0, rExt = 0, rF = 0, zsum = 0;
-      uint32_t d = base;
-      uint64_t* fr = stk + (uint64_t)d * F;
-      bool expand = false;
-      if (!overflow) {
-        if (!cont) {
-          rP = lane < (int)wp ? full_word(p, lane) : 0;
-          if (EXCL && lane < (int)wp) rF = F0[lane];
-          for (uint32_t k = lane; k < wx; k += kWave) fr[O_XX + k] = full_word(x, k);
-          const uint32_t r0 = readlane32(a.sub.r0[s], 0);
-          zsum = mix64(r0);
-          if (lane == 0) kG[0] = r0;
-          if (EXCL) {
-            const uint32_t r1 = readlane32(a.sub.r1[s], 0);
-            zsum += mix64(r1);
-            if (lane == 0) kG[1] = r1;
-          }
-          expand = true;
-        } else {
-          const uint32_t klen = (uint32_t)readlane64(rec[R_KLEN], 0);
-          for (uint32_t k = lane; k < F; k += kWave) fr[k] = rec[R_HDR + k];
-          for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + R_HDR + F))[j];
-          __threadfence_block();
-          if (lane < (int)wp) {
-            rP = fr[lane];
-            rXp = fr[O_XP + lane];
-            rExt = fr[O_EXT + lane];
-            if (EXCL) rF = fr[O_FB + lane];
-          }
-          zsum = readlane64(fr[O_Z], 0);
-        }
-      }
-      if (cont) {
-        __threadfence_block();
-        if (lane == 0) pool_push(a, blk);
-      }
-      WideCtx wctx;
-      wctx.stk = stk;
-      wctx.kG = kG;
-      wctx.F = F;
-      wctx.wp = wp;
-      wctx.base = base;
-      wctx.top = base;
-      wctx.s = s;
-      wctx.kroot = kroot;
-
-      while (!overflow) {
-        bool do_pop = false;
-        if (expand) {
-          expand = false;
-          if (ballot(rP != 0) == 0) {
-            ++acc.tn;
-            // cand empty: K is maximal iff fini is empty too
-            bool xe = ballot(rXp != 0) == 0;
-            if (xe) {
-              bool nz = false;
-              for (uint32_t k = lane; k < wx; k += kWave) nz |= fr[O_XX + k] != 0;
-              xe = ballot(nz) == 0;
-            }
-            if (xe) emit(a, acc, L.hist, zsum, kroot + d, kG);
-            do_pop = true;
-          } else {
-            if (lane < (int)wp) L.sP[lane] = rP;
-            __syncthreads();
-            uint32_t p_cnt = 0;
-            for (uint32_t j = 0; j < wp; ++j) p_cnt += (uint32_t)__popcll(L.sP[j]);
-            // One pass over the rows of P u X: t_u for the pivot and, when
-            // |cand| <= 64, the fini vertices with a neighbour in cand (the
-            // vertices a re-based node keeps; give up beyond 64).
-            bool ok = p_cnt <= 64 && kroot + d + kCFrames <= kcap;
-            uint32_t nx = 0;
-            uint64_t best = 0;
-            uint32_t bu = 0;
-            uint32_t s_mem = 0;
-            // one 64-row chunk: member mask M, fini members MX, first row u0
-            auto chunk = [&](uint64_t M, uint64_t MX, uint32_t u0) {
-              s_mem += (uint32_t)__popcll(M);
-              const uint32_t u = u0 + lane;
-              uint32_t tu = 0;
-              if ((M >> lane) & 1ULL) {
-                for (uint32_t j = 0; j < wp; ++j) tu += (uint32_t)__popcll(L.sP[j] & rowP[(uint64_t)j * nrow + u]);
-                const uint64_t key = ((uint64_t)tu << 32) | (0xFFFFFFFFu - gid[u]);
-                if (key > best) {
-                  best = key;
-                  bu = u;
-                }
-              }
-              if (ok) {
-                const bool keepx = ((MX >> lane) & 1ULL) && tu > 0;
-                const uint64_t b = ballot(keepx);
-                const uint32_t cnt = (uint32_t)__popcll(b);
-                if (nx + cnt > 64) {
-                  ok = false;
-                } else {
-                  if (keepx) L.xl[nx + mask_prefix(b, lane)] = u;
-                  nx += cnt;
-                }
-              }
-            };
-            const uint64_t mem = rP | rXp;
-            for (uint32_t k = 0; k < wp; ++k) {
-              const uint64_t M = readlane64(mem, k);
-              if (M) chunk(M, readlane64(rXp, k), k * 64);
-            }
-            // fini words of the root fini: loaded lane-parallel, only non-zero words visited
-            for (uint32_t kb = 0; kb < wx; kb += kWave) {
-              const uint64_t xw = kb + lane < wx ? fr[O_XX + kb + lane] : 0;
-              uint64_t nzm = ballot(xw != 0);
-              while (nzm) {
-                const uint32_t jj = (uint32_t)__builtin_ctzll(nzm);
-                nzm &= nzm - 1;
-                const uint64_t M = readlane64(xw, jj);
-                chunk(M, M, p + (kb + jj) * 64);
-              }
-            }
-            bool rebased = false;
-            if (ok) {
-                // re-base this node and search its subtree in compact form,
-                // here or (handed off) in the compact kernel
-                const uint64_t tr = now();
-                stat_add(dg.rebases, 1);
-                __syncthreads();
-                const uint32_t ux = lane < (int)nx ? L.xl[lane] : 0;
-                wctx.top = d;
-                const bool handed = a.hand && kroot + d <= kHandK &&
-                                    hand_off<EXCL>(a, kG, s, wp, rP, rF, ux, p_cnt, nx, zsum, kroot + d);
-                if (handed) {
-                  // a handed-off subtree is work done here as far as donation
-                  // pacing goes, else the wide frames would rarely be offered
-                  since += a.donate_interval / 16 + 1;
-                  stat_add(dg.t_rebase, now() - tr);
-                } else {
-                  Compact c;
-                  uint32_t gX;
-                  uint64_t Fc;
-                  compact_gather<EXCL>(rowP, excl, gid, nrow, wp, rP, rF, ux, p_cnt, nx, c, gX, Fc);
-                  c.keyX = gX;
-                  compact_keys(c);
-                  const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
-                  const uint64_t X0 = nx == 64 ? ~0ULL : ((1ULL << nx) - 1);
-                  stat_add(dg.t_rebase, now() - tr);
-                  if (bigk)
-                    compact_dfs<EXCL, true>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv,
-                                            can_donate, since, &wctx, dg);
-                  else
-                    compact_dfs<EXCL, false>(a, L, gK, c, s, P0, 0, X0, 0, 0, Fc, zsum, true, kroot + d, wv,
-                                             can_donate, since, &wctx, dg);
-                }
-                rebased = true;
-                do_pop = true;
-            }
-            if (!rebased) {
-              ++acc.tn;
-              // pivot: largest |P n Gamma(u)| over u in P u X, smallest id on ties
-              const uint64_t mx = wave_max_u64(best);
-              const int wl = __ffsll((unsigned long long)ballot(best == mx)) - 1;
-              const uint32_t piv = readlane32(bu, wl);
-              rExt = lane < (int)wp ? (rP & ~rowP[(uint64_t)lane * nrow + piv]) : 0;
-              const uint64_t n_ext = wave_sum_u64((uint64_t)__popcll(rExt));
-              acc.ssum += s_mem;
-              acc.esum += n_ext;
-              if (ksplit > 1 && !cont && d == 0)
-                rExt = split_root<EXCL>(a, kG, fr, F, wp, s, kroot, rP, rXp, rExt, rF, zsum, ksplit, can_donate);
-            }
-            __syncthreads();
-          }
-        }
-        if (!do_pop) {
-          const uint64_t m = ballot(rExt != 0);
-          if (m == 0) {
-            do_pop = true;
-          } else {
-            const int kq = __ffsll((unsigned long long)m) - 1;
-            const uint64_t w = readlane64(rExt, kq);
-            const int b = __ffsll((unsigned long long)w) - 1;
-            const uint32_t q = (uint32_t)kq * 64 + b;
-            const uint64_t qb = lane == kq ? (1ULL << b) : 0;
-            rExt &= ~qb;
-            if (EXCL && ((readlane64(rF, kq) >> b) & 1ULL)) {
-              // K u {q} would contain an excluded edge: q moves to fini unvisited
-              rP &= ~qb;
-              rXp |= qb;
-              continue;
-            }
-            if (d + 2 > cap || kroot + d + 1 >= kcap) {
-              overflow = true;
-              break;
-            }
-            const uint64_t rq = lane < (int)wp ? rowP[(uint64_t)lane * nrow + q] : 0;
-            const uint64_t cP = rP & rq, cXp = rXp & rq;
-            rP &= ~qb;
-            rXp |= qb;
-            uint64_t* ch = fr + F;
-            if (lane < (int)wp) {
-              fr[lane] = rP;
-              fr[O_XP + lane] = rXp;
-              fr[O_EXT + lane] = rExt;
-              if (EXCL) fr[O_FB + lane] = rF;
-            }
-            for (uint32_t k = lane; k < wx; k += kWave) ch[O_XX + k] = fr[O_XX + k] & rowPX[(uint64_t)q * wx + k];
-            uint64_t cF = 0;
-            if (EXCL && lane < (int)wp) cF = rF | excl[(uint64_t)q * wp + lane];
-            const uint32_t gq = gid[q];
-            if (lane == 0) {
-              fr[O_Z] = zsum;
-              kG[kroot + d] = gq;
-            }
-            zsum += mix64(gq);
-            if (lane == 0) ch[O_Z] = zsum;
-            __threadfence_block();
-            fr = ch;
-            ++d;
-            rP = cP;
-            rXp = cXp;
-            rF = cF;
-            rExt = 0;
-            expand = true;
-
-            // hand the second half of the shallowest unvisited siblings to idle waves
-            if (can_donate && ++since >= a.donate_interval) {
-              since = 0;
-              stat_add(dg.t_donate, 0 - now());
-              wctx.top = d;
-              if (starving(a)) {
-                stat_add(dg.attempts, 1);
-                donate_wide(a, L, wctx, can_donate);
-              }
-              stat_add(dg.t_donate, now());
-            }
-            continue;
-          }
-        }
-        // pop
-        if (d == base) break;
-        fr -= F;
-        --d;
-        if (lane < (int)wp) {
-          rP = fr[lane];
-          rXp = fr[O_XP + lane];
-          rExt = fr[O_EXT + lane];
-          if (EXCL) rF = fr[O_FB + lane];
-        }
-        zsum = readlane64(fr[O_Z], 0);
-      }
+      // masks of subproblems with more than 64 cand words take two words a lane
+      if (p > 64 * 64)
+        wide_task<EXCL, 2>(a, L, lds_stack, gstk, gK, cont, blk, rec, s, ksplit, p, x, wv, bigk, kG, kcap, acc,
+                           overflow, can_donate, since, dg);
+      else
+        wide_task<EXCL, 1>(a, L, lds_stack, gstk, gK, cont, blk, rec, s, ksplit, p, x, wv, bigk, kG, kcap, acc,
+                           overflow, can_donate, since, dg);
     }
 
     if (overflow) {

@@ -85,7 +85,11 @@ namespace {
 inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
 
 constexpr uint32_t kSubMaxK = 64;     // largest new clique the bitmask subsumed kernel takes
-constexpr uint32_t kBigK = kMaxCand + 2;  // largest new clique of any edge subproblem (|K| = 2 + |cand|)
+// common neighbours of a batch edge (an edge subproblem's cand): below the
+// static search's limit, which keeps the large-clique subsumed kernel's LDS
+// table within one workgroup's share
+constexpr uint32_t kMaxCandEdge = 4096;
+constexpr uint32_t kBigK = kMaxCandEdge + 2;  // largest new clique of any edge subproblem (|K| = 2 + |cand|)
 constexpr uint32_t kBigInvolved = 64;     // batch-edge endpoints inside one large new clique
 constexpr uint32_t kSubMaxS = 1024;   // candidate subsets per new clique
 constexpr uint32_t kSubMaxPairs = 256;
@@ -1067,9 +1071,9 @@ int phase_a(imce_state* st, const uint32_t* src, const uint32_t* dst, uint64_t r
   MCE_TRY_HIP(hipMemcpyAsync(&tl[2], st->goff.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
   MCE_TRY_HIP(hipMemcpyAsync(&tl[3], st->gwords.as<uint64_t>() + m - 1, 8, hipMemcpyDeviceToHost, s));
   MCE_TRY_HIP(hipStreamSynchronize(s));
-  if (stats[0] > kMaxCand) {
+  if (stats[0] > kMaxCandEdge) {
     set_error("an edge subproblem has %llu common neighbours; at most %u are supported",
-              (unsigned long long)stats[0], kMaxCand);
+              (unsigned long long)stats[0], kMaxCandEdge);
     return MCE_ENOTSUP;
   }
   const uint64_t aw = std::max<uint64_t>(tl[0] + tl[1], 1), gw = std::max<uint64_t>(tl[2] + tl[3], 1);

@@ -29,7 +29,7 @@ void set_error(const char* fmt, ...);
   } while (0)
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kMaxCand = 4096;  // |cand| per subproblem: 64 words of 64 bits
+constexpr uint32_t kMaxCand = 8192;  // |cand| per subproblem: 128 words of 64 bits
 constexpr uint32_t kBlockWords = 1024;  // one donated-task record
 // K list of a search wave in LDS: enough for subproblems whose cliques stay
 // below 512 vertices.

@@ -1,11 +1,13 @@
 """The supported envelope at its edges: cliques longer than the search wave's
-LDS K list (512 vertices), up to the largest candidate set (4096), and new
-cliques of more than 64 vertices in the incremental step.
+LDS K list (512 vertices), candidate sets past one 64-bit word per lane (4096)
+up to the largest (8192), and new cliques of more than 64 vertices in the
+incremental step.
 
 Bar: bit-exact against the oracle (count, set hash, search nodes,
 per-subproblem triples, clique sets); where the oracle would take minutes
-(K_4097) against the closed forms that pin it on small graphs (one clique,
-2n - 1 search nodes under degree rank, the chain of n nodes at vertex 0).
+(K_4097 and beyond) against the closed forms that pin it on small graphs (one
+clique, 2n - 1 search nodes under degree rank, the chain of n nodes at
+vertex 0).
 """
 
 import numpy as np
@@ -50,12 +52,14 @@ def test_complete_graphs_beyond_the_lds_k_list(m, n):
     assert got["count"] == 1 and got["nodes_total"] == 2 * n - 1
 
 
-def test_complete_graph_at_the_candidate_limit(m):
-    n = 4097  # vertex 0 has 4096 candidates, the largest supported set
+# vertex 0 has n - 1 candidates: the largest set of one word per lane (4096)
+# and the smallest of two (the largest supported set, 8192, is the hub's below)
+@pytest.mark.parametrize("n", [4097, 4098])
+def test_complete_graph_up_to_the_candidate_limit(m, n):
     print("K_%d" % n, flush=True)
     g = gg.complete(n)
     got = m.mce_static(g, rank="degree", cliques=True, per_vertex=True)
-    assert got["max_cand"] == 4096
+    assert got["max_cand"] == n - 1
     assert (got["count"], got["set_hash"], got["nodes_total"]) == (1, O.clique_hash(range(n)), 2 * n - 1)
     assert got["cliques"] == [tuple(range(n))]
     nodes = _u64(got["nodes_v"])
@@ -65,7 +69,65 @@ def test_complete_graph_at_the_candidate_limit(m):
 def test_candidate_set_above_the_limit_is_rejected(m):
     import paper_2001_11433_amd as mod
     with pytest.raises(mod.MceError) as e:
-        m.mce_static(gg.complete(4098), rank="degree")
+        m.mce_static(gg.complete(8194), rank="degree")
+    assert e.value.code == -5  # MCE_ENOTSUP
+
+
+def _hub(n, p, k, seed=51):
+    """ER(n, p) on vertices 1..n plus vertex 0 adjacent to k of them: vertex 0
+    has degree exactly k, the largest, and the smallest id."""
+    base = gg.er(n, p, seed=seed)
+    u0, v0 = gg.edges_of(base)
+    nb = np.sort(np.random.default_rng(seed + 1).choice(n, k, replace=False)) + 1
+    return gg.csr_from_edges(n + 1, np.concatenate([u0 + 1, np.zeros(k, dtype=u0.dtype)]),
+                             np.concatenate([v0 + 1, nb.astype(v0.dtype)]))
+
+
+@pytest.mark.parametrize("kw", [{}, {"donate_interval": 1, "waves_per_cu": 16}], ids=["default", "donation"])
+def test_two_word_candidate_set_in_the_ttt_root_split(m, kw):
+    # the root's pivot is the hub; its child has the hub's 7000 neighbours as cand
+    g = _hub(8000, 0.0012, 7000)
+    print("hub 7000, ttt_root", kw, flush=True)
+    got = m.mce_static(g, rank="ttt_root", **kw)
+    assert got["max_cand"] == 7000
+    want = O.mce_root(g)
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == want
+
+
+def test_two_word_candidate_set_under_degeneracy_rank(m):
+    # the hub shares the core number of most of its neighbours and has the
+    # smallest id, so it owns them: a subproblem of about 6000 candidates
+    g = _hub(8000, 0.0012, 7000)
+    print("hub 7000, degeneracy", flush=True)
+    got = _check(m, g, "degeneracy")
+    assert got["max_cand"] > 4096
+
+
+def test_two_word_root_split(m):
+    # the hub's subproblem dominates the cost and is dealt out at launch
+    import torch
+    g = _hub(8000, 0.0012, 7000)
+    want = O.mce_parmce(g, "degeneracy", threads=8)
+    cost = torch.from_numpy(np.log(want.nodes_v.astype(np.float64) + 1.0).astype(np.float32)).cuda()
+    print("hub 7000, degeneracy, split 64", flush=True)
+    got = m.mce_static(g, rank="degeneracy", sched="cost", cost=cost, split=64, waves_per_cu=4, per_vertex=True)
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == (want.count, want.set_hash, want.nodes)
+    assert np.array_equal(_u64(got["nodes_v"]), want.nodes_v)
+    assert got["donated"] > 0
+
+
+def test_ttt_root_at_the_candidate_limit(m):
+    g = _hub(9000, 0.001, 8192)
+    print("hub 8192, ttt_root", flush=True)
+    got = m.mce_static(g, rank="ttt_root")
+    assert got["max_cand"] == 8192
+    assert (got["count"], got["set_hash"], got["nodes_total"]) == O.mce_root(g)
+
+
+def test_ttt_root_above_the_limit_is_rejected(m):
+    import paper_2001_11433_amd as mod
+    with pytest.raises(mod.MceError) as e:
+        m.mce_static(_hub(9000, 0.001, 8193), rank="ttt_root")
     assert e.value.code == -5  # MCE_ENOTSUP
 
 
