@@ -885,14 +885,14 @@ __device__ __forceinline__ uint32_t hand_words(uint32_t wp, uint32_t nx, uint32_
 }
 
 // Re-bases a wide node onto the compact 64 + 64 universe: gathers the rows of
-// its candidates (the set bits of the wide mask rP, NW words to a lane, in
+// its candidates (the set bits of the wide mask whose word k is wordP(k), in
 // ascending order) and of its kept fini vertices (local row ux, lane < nx)
 // from the subproblem's bit rows.  Sets c (rows, ids, np, nx), the fini ids
 // gX (lane < nx) and, with exclusion, the compact mask of candidates whose
-// branch is excluded (from the wide mask rF, laid out like rP).
-template <bool EXCL, int NW>
+// branch is excluded (from the wide mask whose word k is wordF(k)).
+template <bool EXCL, class WordP, class WordF>
 __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const uint32_t* gid, uint64_t nrow,
-                               uint32_t wp, const uint64_t (&rP)[NW], const uint64_t (&rF)[NW], uint32_t ux,
+                               uint32_t wp, const WordP& wordP, const WordF& wordF, uint32_t ux,
                                uint32_t np, uint32_t nx, Compact& c, uint32_t& gX, uint64_t& Fc) {
   const int lane = lane_id();
   c.np = np;
@@ -901,7 +901,7 @@ __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const
   {
     uint32_t j = 0;
     for (uint32_t k = 0; k < wp; ++k) {
-      uint64_t m = word_of(rP, k);
+      uint64_t m = wordP(k);
       while (m) {
         const uint32_t b = (uint32_t)__builtin_ctzll(m);
         if (lane == (int)j) pm = k * 64 + b;
@@ -913,12 +913,12 @@ __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const
   uint64_t cPP = 0, cXP = 0, cEx = 0, cF = 0;
   uint32_t cnt = 0;
   for (uint32_t k = 0; k < wp; ++k) {
-    uint64_t m = word_of(rP, k);
+    uint64_t m = wordP(k);
     if (m == 0) continue;
     const uint64_t wP = lane < (int)np ? rowP[(uint64_t)k * nrow + pm] : 0;
     const uint64_t wX = lane < (int)nx ? rowP[(uint64_t)k * nrow + ux] : 0;
     const uint64_t wE = (EXCL && lane < (int)np) ? excl[(uint64_t)pm * wp + k] : 0;
-    const uint64_t fk = EXCL ? word_of(rF, k) : 0;
+    const uint64_t fk = EXCL ? wordF(k) : 0;
     while (m) {
       const uint32_t b = (uint32_t)__builtin_ctzll(m);
       cPP |= ((wP >> b) & 1ULL) << cnt;
@@ -952,9 +952,10 @@ __device__ void compact_gather(const uint64_t* rowP, const uint64_t* excl, const
 // itself (compact_gather), so a record holds no row data.  False when the
 // arena or the index is full (the request still counts, so the host learns
 // the size it needs).
-template <bool EXCL>
-__device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint32_t wp, uint64_t rP, uint64_t rF,
-                         uint32_t ux, uint32_t np, uint32_t nx, uint64_t zsum, uint32_t klen) {
+template <bool EXCL, int NW>
+__device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint32_t wp, const uint64_t (&rP)[NW],
+                         const uint64_t (&rF)[NW], uint32_t ux, uint32_t np, uint32_t nx, uint64_t zsum,
+                         uint32_t klen) {
   const int lane = lane_id();
   const uint32_t units = (hand_words(wp, nx, klen, EXCL) + 7) / 8;
   uint64_t old = 0;
@@ -973,10 +974,18 @@ __device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint
     fetch_add(&a.ctl[CTL_HANDOK], 1);
   }
   uint64_t* w = rec + 4;
-  if (lane < (int)wp) w[lane] = rP;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint32_t j = (uint32_t)lane + 64u * i;
+    if (j < wp) w[j] = rP[i];
+  }
   w += wp;
   if (EXCL) {
-    if (lane < (int)wp) w[lane] = rF;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t j = (uint32_t)lane + 64u * i;
+      if (j < wp) w[j] = rF[i];
+    }
     w += wp;
   }
   uint32_t* u = (uint32_t*)w;
@@ -1002,20 +1011,15 @@ __device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compac
   const uint64_t* rowG = a.arena + readlane64(a.sub.off[s], 0);
   const uint64_t* excl = rowG + (uint64_t)wp * nrow + (uint64_t)p * wx;
   const uint32_t* gid = a.gids + readlane64(a.sub.goff[s], 0);
-  // records come only from subproblems of at most 64 cand words
-  const uint64_t* w = rec + 4;
-  const uint64_t rP[1] = {lane < (int)wp ? w[lane] : 0};
-  w += wp;
-  uint64_t rF[1] = {0};
-  if (EXCL) {
-    rF[0] = lane < (int)wp ? w[lane] : 0;
-    w += wp;
-  }
-  const uint32_t* u = (const uint32_t*)w;
+  // the record's wide masks, word k read where the gather needs it
+  const uint64_t* wP = rec + 4;
+  const uint64_t* wF = wP + wp;
+  const uint32_t* u = (const uint32_t*)(wP + (EXCL ? 2 : 1) * wp);
   const uint32_t ux = lane < (int)nx ? u[lane] : 0;
   for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[nx + j];
   uint32_t gX;
-  compact_gather<EXCL, 1>(rowG, excl, gid, nrow, wp, rP, rF, ux, np, nx, c, gX, F);
+  compact_gather<EXCL>(rowG, excl, gid, nrow, wp, [&](uint32_t k) { return wP[k]; },
+                       [&](uint32_t k) { return EXCL ? wF[k] : 0ULL; }, ux, np, nx, c, gX, F);
   c.keyX = gX;
   compact_keys(c);
   P = np == 64 ? ~0ULL : ((1ULL << np) - 1);
@@ -1025,7 +1029,7 @@ __device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compac
 // One wide task: a subproblem's root or a donated wide continuation, searched
 // with its node masks NW words to a lane (word j in lane j % 64 of register
 // j / 64).  Descends until a node's cand fits the compact universe, then
-// re-bases it (searched here, or handed to the compact kernel when NW is 1).
+// re-bases it (searched here, or handed to the compact kernel).
 template <bool EXCL, int NW>
 __device__ __forceinline__ void wide_task(const EnumArgs& a, Lds& L, uint64_t* lds_stack, uint64_t* gstk,
                                           uint32_t* gK, bool cont, uint32_t blk, const uint64_t* rec, uint32_t s,
@@ -1209,10 +1213,8 @@ __device__ __forceinline__ void wide_task(const EnumArgs& a, Lds& L, uint64_t* l
           __syncthreads();
           const uint32_t ux = lane < (int)nx ? L.xl[lane] : 0;
           wctx.top = d;
-          bool handed = false;
-          if constexpr (NW == 1)
-            handed = a.hand && kroot + d <= kHandK &&
-                     hand_off<EXCL>(a, kG, s, wp, rP[0], rF[0], ux, p_cnt, nx, zsum, kroot + d);
+          const bool handed = a.hand && kroot + d <= kHandK &&
+                              hand_off<EXCL, NW>(a, kG, s, wp, rP, rF, ux, p_cnt, nx, zsum, kroot + d);
           if (handed) {
             // a handed-off subtree is work done here as far as donation
             // pacing goes, else the wide frames would rarely be offered
@@ -1222,7 +1224,8 @@ __device__ __forceinline__ void wide_task(const EnumArgs& a, Lds& L, uint64_t* l
             Compact c;
             uint32_t gX;
             uint64_t Fc;
-            compact_gather<EXCL, NW>(rowP, excl, gid, nrow, wp, rP, rF, ux, p_cnt, nx, c, gX, Fc);
+            compact_gather<EXCL>(rowP, excl, gid, nrow, wp, [&](uint32_t k) { return word_of(rP, k); },
+                                 [&](uint32_t k) { return word_of(rF, k); }, ux, p_cnt, nx, c, gX, Fc);
             c.keyX = gX;
             compact_keys(c);
             const uint64_t P0 = c.np == 64 ? ~0ULL : ((1ULL << c.np) - 1);
