@@ -609,7 +609,7 @@ __device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
 //
 // Entry: expand = true starts at the node (P, Xp, Xx) itself; expand = false
 // resumes a node whose deep children D are left (a donated record).
-template <bool EXCL, bool BIGK, class LT>
+template <bool EXCL, bool BIGK, class LT, bool EXTRA = true>
 __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* gK, const Compact& c, uint32_t s, uint64_t P,
                             uint64_t Xp, uint64_t Xx, uint64_t ext, uint64_t D, uint64_t F, uint64_t zsum,
                             bool expand, uint32_t kbase, uint32_t wv, bool& can_donate, uint32_t& since,
@@ -636,7 +636,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
         if ((Xp | Xx) == 0) {
           T.tc += 1;
           if (lane == 0) T.vh += clique_term(zsum, kl);
-          if (a.emit_extra) {
+          if (EXTRA && a.emit_extra) {
             if (a.cl_vert) store_clique(a, kl, kG);
             if (a.hist) hist_add(a, L.hist, kl);
           }
@@ -697,7 +697,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
             const bool two = (grandm >> lane) & 1ULL;
             T.vh += mix64((two ? b2 + zw : b1) + c.zP);
           }
-          if (a.emit_extra) {
+          if (EXTRA && a.emit_extra) {
             uint64_t cm = cliqm;
             while (cm) {
               const uint32_t q = (uint32_t)__builtin_ctzll(cm);
@@ -1493,7 +1493,9 @@ __global__ void __launch_bounds__(64) k_enum(EnumArgs a) {
 // bit 62 | record) and the compact donations among its own waves (bit 63 |
 // pool block).  Its register footprint is a fraction of k_enum's, so many
 // more waves fit per SIMD to hide the latency of the search's serial chain.
-template <bool EXCL>
+// EXTRA: the launch writes cliques out or tallies their sizes (else the
+// search loop carries no test for it).
+template <bool EXCL, bool EXTRA>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_compact(EnumArgs a) {
   __shared__ LdsC L;
   const int lane = threadIdx.x;
@@ -1529,8 +1531,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
     const uint32_t wv = (p + x + 31) / 32;
-    compact_dfs<EXCL, false>(a, L, nullptr, c, s, P, Xp, Xx, ext, D, F, zsum, !pooled, klen, wv, can_donate,
-                             since, (const WideCtx*)nullptr, dg);
+    compact_dfs<EXCL, false, LdsC, EXTRA>(a, L, nullptr, c, s, P, Xp, Xx, ext, D, F, zsum, !pooled, klen, wv,
+                                          can_donate, since, (const WideCtx*)nullptr, dg);
     if (lane == 0) {
       const Acc t = L.st.cacc;
       L.st.cacc = Acc{};
@@ -1584,10 +1586,17 @@ __global__ void k_finish_offsets(uint64_t* off, uint64_t nc, uint64_t nv) { off[
 }  // namespace
 
 hipError_t launch_compact(const EnumArgs& a, uint32_t grid, bool exclusion, hipStream_t s) {
-  if (exclusion)
-    hipLaunchKernelGGL(k_compact<true>, dim3(grid), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_compact<false>, dim3(grid), dim3(64), 0, s, a);
+  if (exclusion) {
+    if (a.emit_extra)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_compact<true, true>), dim3(grid), dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_compact<true, false>), dim3(grid), dim3(64), 0, s, a);
+  } else {
+    if (a.emit_extra)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_compact<false, true>), dim3(grid), dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_compact<false, false>), dim3(grid), dim3(64), 0, s, a);
+  }
   return hipGetLastError();
 }
 
