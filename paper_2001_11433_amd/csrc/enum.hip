@@ -590,7 +590,7 @@ __device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
 }
 
 // Frame of a compact node with deep children still to visit (kCF words):
-//   0 cand P   1 fini from cand Xp   2 fini from the root fini Xx   3 ext
+//   0 cand P   1 PX = P u Xp         2 fini from the root fini Xx   3 ext
 //   4 zsum     5 excluded-edge mask F  6 |K|                       7 D
 // where D = the deep children (two or more candidates) not yet visited.  A
 // child q's (cand, fini) follow from the node's by Algorithm 3's formula:
@@ -606,6 +606,9 @@ __device__ __forceinline__ uint32_t lanes_select(uint64_t lanes, uint32_t v) {
 // ext empty, or the branch on w is excluded).  The remaining "deep" children
 // are visited in ascending order by descending into them.  The recursion
 // tree, and with it every count, is the sequential one.
+//
+// The search keeps PX = P u Xp (Xp: the fini vertices from the cand universe)
+// rather than Xp: a child's PX is PX n Gamma(q), and Xp = PX \ P.
 //
 // Entry: expand = true starts at the node (P, Xp, Xx) itself; expand = false
 // resumes a node whose deep children D are left (a donated record).
@@ -623,6 +626,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
   // search nodes between donation checks (also the tallies' flush interval)
   const uint32_t dlim = a.donate_interval < (1u << 14) ? 4 * a.donate_interval : (1u << 16);
   const uint64_t lower = (1ULL << lane) - 1;  // the children before this lane's
+  uint64_t PX = P | Xp;
   VTally T;
   T.init();
   for (;;) {
@@ -633,7 +637,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
       D = 0;
       if (P == 0) {
         // only a task's first node can arrive here with an empty cand
-        if ((Xp | Xx) == 0) {
+        if ((PX | Xx) == 0) {
           T.tc += 1;
           if (lane == 0) T.vh += clique_term(zsum, kl);
           if (EXTRA && a.emit_extra) {
@@ -643,20 +647,20 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
         }
       } else {
         // pivot: largest |P n Gamma(u)| over u in P u X, smallest id on ties
-        const uint32_t k1 = lanes_select(P | Xp, ((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP);
+        const uint32_t k1 = lanes_select(PX, ((uint32_t)__popcll(P & c.rowPP) << 16) | c.keyP);
         const uint32_t k2 = lanes_select(Xx, ((uint32_t)__popcll(P & c.rowXP) << 16) | c.keyX);
         const uint32_t mx = wave_max_u32(k1 > k2 ? k1 : k2);
         const uint32_t row = mx & 0xFFu;
         const uint64_t prow = row < 64 ? readlane64(c.rowPP, row) : readlane64(c.rowXP, row & 63);
         ext = P & ~prow;
-        T.ss += (uint32_t)(__popcll(P) + __popcll(Xp) + __popcll(Xx));
+        T.ss += (uint32_t)(__popcll(PX) + __popcll(Xx));
         T.es += (uint32_t)__popcll(ext);
         // the child pass: lane q forms child q's cand and fini; the lane masks
         // of the children that are leaves or have one candidate decide them
         const uint64_t chm = EXCL ? (ext & ~F) : ext;  // excluded q join fini unvisited
         const uint64_t below = ext & lower;
         const uint64_t cP = (P & ~below) & c.rowPP;
-        const uint64_t cXp = (Xp | below) & c.rowPP;
+        const uint64_t cXp = (PX & c.rowPP) & ~cP;
         const uint64_t cXx = Xx & c.rowPX;
         const uint32_t pc = (uint32_t)__popcll(cP);
         const uint64_t zm = ballot(pc == 0);
@@ -722,7 +726,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
       if (d == 0) break;
       const uint64_t v = lane < (int)kCF ? L.cstk[(d - 1) * kCF + lane] : 0;
       P = readlane64(v, 0);
-      Xp = readlane64(v, 1);
+      PX = readlane64(v, 1);
       Xx = readlane64(v, 2);
       ext = readlane64(v, 3);
       zsum = readlane64(v, 4);
@@ -741,7 +745,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
         if (lane == 0) {
           uint64_t* f = &L.cstk[d * kCF];
           f[0] = P;
-          f[1] = Xp;
+          f[1] = PX;
           f[2] = Xx;
           f[3] = ext;
           f[4] = zsum;
@@ -759,7 +763,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
     const uint64_t rqx = readlane64(c.rowPX, q);
     if (lane == 0) kG[kl] = readlane32(c.gP, q);
     ++kl;
-    Xp = (Xp | below) & rq;
+    PX &= rq;
     P = (P & ~below) & rq;
     Xx &= rqx;
     if (EXCL) F |= readlane64(c.rowEx, q);
