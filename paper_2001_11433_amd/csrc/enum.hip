@@ -660,12 +660,15 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
         const uint64_t chm = EXCL ? (ext & ~F) : ext;  // excluded q join fini unvisited
         const uint64_t below = ext & lower;
         const uint64_t cP = (P & ~below) & c.rowPP;
-        const uint64_t cXp = (PX & c.rowPP) & ~cP;
+        // the child's PX (its Xp plus cP): for a leaf it is the child's Xp, and
+        // for a one-candidate child it differs from Xp only in w, which is
+        // never adjacent to itself
+        const uint64_t cPX = PX & c.rowPP;
         const uint64_t cXx = Xx & c.rowPX;
         const uint32_t pc = (uint32_t)__popcll(cP);
         const uint64_t zm = ballot(pc == 0);
         const uint64_t om = ballot(pc == 1);
-        const uint64_t fm = ballot((cXp | cXx) == 0);
+        const uint64_t fm = ballot((cPX | cXx) == 0);
         const uint64_t leafm = chm & zm;
         const uint64_t onem = chm & om;
         D = chm & ~(zm | om);
@@ -680,7 +683,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
           w = pc ? (uint32_t)__builtin_ctzll(cP) : 0u;
           const uint64_t rw = bpermute64(c.rowPP, w);
           const uint64_t rwx = bpermute64(c.rowPX, w);
-          const uint64_t blk = ballot(((cXp & rw) | (cXx & rwx)) != 0);
+          const uint64_t blk = ballot(((cPX & rw) | (cXx & rwx)) != 0);
           uint64_t ok = onem & ~blk;
           if (EXCL) ok &= ~ballot((((F | c.rowEx) >> w) & 1ULL) != 0);
           grandm = ok;
@@ -688,7 +691,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
           T.tn += (uint32_t)__popcll(grandm);
           T.es += (uint32_t)__popcll(onem & ~blk);
           // the child's pivot step, counted like an expanded node's
-          if ((onem >> lane) & 1ULL) T.vss += 1u + (uint32_t)__popcll(cXp) + (uint32_t)__popcll(cXx);
+          if ((onem >> lane) & 1ULL) T.vss += (uint32_t)__popcll(cPX) + (uint32_t)__popcll(cXx);
         }
         if (cliqm) {
           T.tc += (uint32_t)__popcll(cliqm);
