@@ -764,7 +764,7 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
     const uint64_t below = ext & ((1ULL << q) - 1);
     const uint64_t rq = readlane64(c.rowPP, q);
     const uint64_t rqx = readlane64(c.rowPX, q);
-    if (lane == 0) kG[kl] = readlane32(c.gP, q);
+    if (EXTRA && lane == 0) kG[kl] = readlane32(c.gP, q);  // K's ids serve only the clique output
     ++kl;
     PX &= rq;
     P = (P & ~below) & rq;
@@ -816,7 +816,8 @@ __device__ __forceinline__ void compact_dfs(const EnumArgs& a, LT& L, uint32_t* 
         rec[kCR_KEY + lane] = (uint64_t)c.keyP | ((uint64_t)c.keyX << 32);
         ((uint32_t*)(rec + kCR_GP))[lane] = c.gP;
         if (BIGK) __syncthreads();  // K entries written by single lanes in global memory
-        for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = kG[j];
+        if (EXTRA)
+          for (uint32_t j = lane; j < klen; j += kWave) ((uint32_t*)(rec + kCR_K))[j] = kG[j];
         if (lane == 0) L.cstk[i * kCF + 7] = km;
         publish_record(a, blk);
       }
@@ -851,7 +852,7 @@ __device__ void compact_keys(Compact& c) {
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
 }
 
-template <bool EXCL>
+template <bool EXCL, bool EXTRA = true>
 __device__ __forceinline__ void compact_from_record(const uint64_t* rec, Compact& c, uint32_t* kG, uint64_t& P, uint64_t& Xp,
                                     uint64_t& Xx, uint64_t& ext, uint64_t& D, uint64_t& zsum, uint64_t& F,
                                     uint32_t& klen) {
@@ -869,7 +870,8 @@ __device__ __forceinline__ void compact_from_record(const uint64_t* rec, Compact
   c.keyX = (uint32_t)(key >> 32);
   c.gP = ((const uint32_t*)(rec + kCR_GP))[lane];
   c.zP = lane < (int)c.np ? mix64(c.gP) : 0;
-  for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
+  if (EXTRA)
+    for (uint32_t j = lane; j < klen; j += kWave) kG[j] = ((const uint32_t*)(rec + kCR_K))[j];
   const uint64_t v = lane < (int)kCF ? rec[R_HDR + lane] : 0;
   P = readlane64(v, 0);
   Xp = readlane64(v, 1);
@@ -882,11 +884,13 @@ __device__ __forceinline__ void compact_from_record(const uint64_t* rec, Compact
 
 // Handoff records (one per re-based node, for the compact kernel, which
 // expands and counts it), in 64-byte units of the handoff arena:
-//   word 0  s | np << 32 | nx << 40      word 1  klen
-//   word 2  zsum                         word 3  excluded-edge mask (F)
-//   rowPP[np], rowXP[nx], rowPX[np], (rowEx[np] with exclusion) as u64
-//   gP[np], gX[nx], K[klen] as u32
-// The tie-break keys are recomputed from gP and gX on the other side.
+//   word 0  s | np << 32 | nx << 40      word 1  |K|
+//   word 2  zsum                         word 3  0
+//   then the node's wide cand mask (wp words) and, with exclusion, its wide
+//   excluded-branch mask (wp words); then as u32 the local rows of its kept
+//   fini vertices (nx) and K's ids (|K| of them, only when the launch writes
+//   cliques out or tallies their sizes: the search needs |K| and zsum only).
+// The compact kernel gathers the compact rows and recomputes the keys.
 __device__ __forceinline__ uint32_t hand_words(uint32_t wp, uint32_t nx, uint32_t klen, bool excl) {
   return 4 + (excl ? 2 : 1) * wp + (nx + klen + 1) / 2;
 }
@@ -964,7 +968,8 @@ __device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint
                          const uint64_t (&rF)[NW], uint32_t ux, uint32_t np, uint32_t nx, uint64_t zsum,
                          uint32_t klen) {
   const int lane = lane_id();
-  const uint32_t units = (hand_words(wp, nx, klen, EXCL) + 7) / 8;
+  const uint32_t kst = a.emit_extra ? klen : 0u;  // K's ids serve only the clique output
+  const uint32_t units = (hand_words(wp, nx, kst, EXCL) + 7) / 8;
   uint64_t old = 0;
   if (lane == 0) old = fetch_add(&a.ctl[CTL_HAND], (1ULL << 32) | units);
   old = readlane64(old, 0);
@@ -997,12 +1002,12 @@ __device__ bool hand_off(const EnumArgs& a, const uint32_t* kG, uint32_t s, uint
   }
   uint32_t* u = (uint32_t*)w;
   if (lane < (int)nx) u[lane] = ux;
-  for (uint32_t j = lane; j < klen; j += kWave) u[nx + j] = kG[j];
+  for (uint32_t j = lane; j < kst; j += kWave) u[nx + j] = kG[j];
   return true;
 }
 
 // Reads a handoff record into compact form (the node still to be expanded).
-template <bool EXCL, class LT>
+template <bool EXCL, bool EXTRA, class LT>
 __device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compact& c, LT& L, uint64_t& P,
                                   uint64_t& Xx, uint64_t& zsum, uint64_t& F, uint32_t& klen, uint32_t& s) {
   const int lane = lane_id();
@@ -1023,7 +1028,8 @@ __device__ void compact_from_hand(const EnumArgs& a, const uint64_t* rec, Compac
   const uint64_t* wF = wP + wp;
   const uint32_t* u = (const uint32_t*)(wP + (EXCL ? 2 : 1) * wp);
   const uint32_t ux = lane < (int)nx ? u[lane] : 0;
-  for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[nx + j];
+  if (EXTRA)
+    for (uint32_t j = lane; j < klen; j += kWave) L.kG[j] = u[nx + j];
   uint32_t gX;
   compact_gather<EXCL>(rowG, excl, gid, nrow, wp, [&](uint32_t k) { return wP[k]; },
                        [&](uint32_t k) { return EXCL ? wF[k] : 0ULL; }, ux, np, nx, c, gX, F);
@@ -1528,12 +1534,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) k_
       // a donation among the compact kernel's own waves
       const uint64_t* rec = a.pool + idx * kBlockWords;
       s = (uint32_t)readlane64(rec[R_S], 0);
-      compact_from_record<EXCL>(rec, c, L.kG, P, Xp, Xx, ext, D, zsum, F, klen);
+      compact_from_record<EXCL, EXTRA>(rec, c, L.kG, P, Xp, Xx, ext, D, zsum, F, klen);
       __threadfence_block();
       if (lane == 0) pool_push(a, (uint32_t)idx);
     } else {
       const uint64_t* rec = a.hand + (uint64_t)a.hand_idx[idx] * 8;
-      compact_from_hand<EXCL>(a, rec, c, L, P, Xx, zsum, F, klen, s);
+      compact_from_hand<EXCL, EXTRA>(a, rec, c, L, P, Xx, zsum, F, klen, s);
     }
     const uint32_t p = readlane32(a.sub.p[s], 0);
     const uint32_t x = readlane32(a.sub.x[s], 0);
