@@ -75,15 +75,32 @@ __global__ void k_sizes(uint64_t n, const uint64_t* __restrict__ rp, const uint3
 
 // One wave per vertex: mark the fini positions of v's row that have a cand
 // neighbour.
-__global__ void __launch_bounds__(256) k_mark(uint64_t n, const uint64_t* __restrict__ rp,
-                                              const uint32_t* __restrict__ col, const uint64_t* __restrict__ metric,
-                                              const uint32_t* __restrict__ P, uint32_t* xmark) {
-  const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+// The sorted neighbour list of v, which every membership test below
+// searches: staged in LDS when it has at most kNbLds entries (nearly every
+// vertex), so the binary searches read LDS rather than L2/HBM.  One wave per
+// block, so the barrier is the wave's.
+constexpr uint32_t kNbLds = 2048;
+
+__device__ __forceinline__ const uint32_t* stage_row(const uint32_t* __restrict__ col, uint64_t vb, uint64_t d,
+                                                     uint32_t* lds) {
+  if (d > kNbLds) return col + vb;
+  for (uint64_t i = lane_id(); i < d; i += kWave) lds[i] = col[vb + i];
+  __syncthreads();
+  return lds;
+}
+
+// One wave (block) per vertex.
+__global__ void __launch_bounds__(64) k_mark(uint64_t n, const uint64_t* __restrict__ rp,
+                                             const uint32_t* __restrict__ col, const uint64_t* __restrict__ metric,
+                                             const uint32_t* __restrict__ P, uint32_t* xmark) {
+  __shared__ uint32_t snb[kNbLds];
+  const uint64_t v = blockIdx.x;
   const int lane = lane_id();
   if (v >= n) return;
   const uint32_t p = P[v];
   const uint64_t vb = rp[v], d = rp[v + 1] - vb;
   if (p == 0 || p == d) return;
+  const uint32_t* nb = stage_row(col, vb, d, snb);
   for (uint64_t c0 = 0; c0 < d; c0 += kWave) {
     uint64_t i = c0 + lane;
     bool isP = i < d && rank_gt(metric, col[vb + i], (uint32_t)v);
@@ -95,7 +112,7 @@ __global__ void __launch_bounds__(256) k_mark(uint64_t n, const uint64_t* __rest
       const uint64_t qb = rp[q], qe = rp[q + 1];
       for (uint64_t j = qb + lane; j < qe; j += kWave) {
         uint32_t y = col[j];
-        int64_t pos = bsearch_u32(col + vb, d, y);
+        int64_t pos = bsearch_u32(nb, d, y);
         if (pos >= 0 && !rank_gt(metric, y, (uint32_t)v)) {
           uint64_t bit = vb + (uint64_t)pos;
           atomicOr(&xmark[bit >> 5], 1u << (bit & 31));
@@ -147,20 +164,22 @@ __global__ void k_words(uint64_t n, const uint64_t* __restrict__ rp, const uint3
 constexpr uint32_t kLidxP = 0x80000000u;
 constexpr uint32_t kLidxNone = 0x7FFFFFFFu;
 
-// One wave per vertex with a non-empty cand: vertex-id table and bit rows.
-__global__ void __launch_bounds__(256) k_build(uint64_t n, const uint64_t* __restrict__ rp,
-                                               const uint32_t* __restrict__ col, const uint64_t* __restrict__ metric,
-                                               const uint32_t* __restrict__ P, const uint32_t* __restrict__ X,
-                                               const uint32_t* __restrict__ xmark, uint32_t* __restrict__ lidx,
-                                               const uint64_t* __restrict__ off, const uint64_t* __restrict__ goff,
-                                               uint64_t* arena, uint32_t* __restrict__ gids) {
-  const uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+// One wave (block) per vertex with a non-empty cand: vertex-id table and bit rows.
+__global__ void __launch_bounds__(64) k_build(uint64_t n, const uint64_t* __restrict__ rp,
+                                              const uint32_t* __restrict__ col, const uint64_t* __restrict__ metric,
+                                              const uint32_t* __restrict__ P, const uint32_t* __restrict__ X,
+                                              const uint32_t* __restrict__ xmark, uint32_t* __restrict__ lidx,
+                                              const uint64_t* __restrict__ off, const uint64_t* __restrict__ goff,
+                                              uint64_t* arena, uint32_t* __restrict__ gids) {
+  __shared__ uint32_t snb[kNbLds];
+  const uint64_t v = blockIdx.x;
   const int lane = lane_id();
   if (v >= n) return;
   const uint32_t p = P[v];
   if (p == 0) return;
   const uint32_t x = X[v];
   const uint64_t vb = rp[v], d = rp[v + 1] - vb;
+  const uint32_t* nb = stage_row(col, vb, d, snb);
   const uint64_t wp = (p + 63) / 64, wx = (x + 63) / 64, nrow = (uint64_t)p + x;
   uint64_t* rowP = arena + off[v];
   uint64_t* rowPX = rowP + wp * nrow;
@@ -202,7 +221,7 @@ __global__ void __launch_bounds__(256) k_build(uint64_t n, const uint64_t* __res
       const uint64_t qb = rp[q], qe = rp[q + 1];
       for (uint64_t j = qb + lane; j < qe; j += kWave) {
         uint32_t y = col[j];
-        int64_t pos = bsearch_u32(col + vb, d, y);
+        int64_t pos = bsearch_u32(nb, d, y);
         if (pos < 0) continue;
         uint32_t L = lidx[vb + pos];
         if (L & kLidxP) {
@@ -301,7 +320,7 @@ hipError_t launch_sizes(uint64_t n, const uint64_t* rp, const uint32_t* col, con
 hipError_t launch_mark(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* metric, BuildBufs b,
                        hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, metric, b.p, b.xmark);
+  hipLaunchKernelGGL(k_mark, dim3((uint32_t)n), dim3(64), 0, s, n, rp, col, metric, b.p, b.xmark);
   return hipGetLastError();
 }
 
@@ -315,7 +334,7 @@ hipError_t launch_words(uint64_t n, const uint64_t* rp, BuildBufs b, hipStream_t
 hipError_t launch_build(uint64_t n, const uint64_t* rp, const uint32_t* col, const uint64_t* metric, BuildBufs b,
                         const uint64_t* off, const uint64_t* goff, uint64_t* arena, uint32_t* gids, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build, dim3(blocks_for(n * 64, 256)), dim3(256), 0, s, n, rp, col, metric, b.p, b.x,
+  hipLaunchKernelGGL(k_build, dim3((uint32_t)n), dim3(64), 0, s, n, rp, col, metric, b.p, b.x,
                      b.xmark, b.lidx, off, goff, arena, gids);
   return hipGetLastError();
 }
