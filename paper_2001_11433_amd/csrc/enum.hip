@@ -15,16 +15,18 @@
 // Two representations of a search node:
 //  * wide: bitsets over the subproblem's local indices (cand 0..p-1, then the
 //    relevant fini vertices), rows in the global arena, lane k holding word k
-//    of P (cand), Xp (fini from cand) and ext; Xx (fini from the root fini)
-//    lives in the frame.  Frames sit in LDS when the deepest possible stack
-//    fits, else in a per-wave global region.
+//    of P (cand), Xp (fini from cand) and ext, and word 64 + k too when cand
+//    has more than 4096 vertices; Xx (fini from the root fini) lives in the
+//    frame.  Frames sit in LDS when the deepest possible stack fits, else in
+//    a per-wave global region.
 //  * compact: once a node has |cand| <= 64 and at most 64 fini vertices with a
 //    neighbour in cand, its subtree is re-based onto a 64 + 64 vertex
 //    universe.  Fini vertices with no neighbour in cand never enter a child's
 //    fini and can only tie as pivot when every t_u is 0, where ext = cand for
 //    any pivot, so dropping them changes neither cliques nor the recursion
 //    tree.  Lane l holds the compact rows of cand vertex l and fini vertex l
-//    (64-bit words) in VGPRs; P, Xp, Xx, ext are wave-uniform 64-bit words.
+//    (64-bit words) in VGPRs; P, PX = P u Xp, Xx and ext are wave-uniform
+//    64-bit words.
 //
 // Pivot (Algorithm 2): t_u = popcount(P & row_u) for every u in P u X in
 // parallel, then a wave max over (t_u, smallest id) picks the pivot.
