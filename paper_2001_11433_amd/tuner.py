@@ -24,7 +24,7 @@ import hashlib
 import json
 import os
 import time
-from typing import Dict, Iterable, Optional, Sequence
+from typing import Dict, Optional, Sequence
 
 import numpy as np
 
