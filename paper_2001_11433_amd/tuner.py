@@ -95,27 +95,34 @@ def lookup(g, rank: str, path: str = TABLE, family: Optional[str] = None) -> dic
 
 def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, space=SPACE,
          time_limit_s: Optional[float] = None, path: Optional[str] = TABLE, log=None, samples: int = SAMPLES,
-         key: Optional[str] = None) -> dict:
+         key: Optional[str] = None, trial=None) -> dict:
     """Grid over `grid`, then a coordinate search over `space` from the best
     grid point, each trial the median enumeration time of `samples` runs;
     returns {"best": knobs, "enum_ms": t, "trials": [...]} and records it
-    under the graph's signature (or `key`)."""
-    dg = _as_device_graph(g)
+    under the graph's signature (or `key`).  `trial(knobs) -> (enum_ms,
+    (count, hash, nodes))` stands in for the device run (the search itself
+    is then testable without a GPU)."""
+    dg = _as_device_graph(g) if trial is None else None
     trials = []
     ref = None
     t_start = time.perf_counter()
+
+    def one(knobs):
+        if trial is not None:
+            return trial(knobs)
+        r = mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(knobs))
+        return r["enum_ms"], (r["count"], r["set_hash"], r["nodes_total"])
 
     def run(knobs):
         nonlocal ref
         ts = []
         for _ in range(samples):
-            r = mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(knobs))
-            got = (r["count"], r["set_hash"], r["nodes_total"])
+            ms, got = one(knobs)
             if ref is None:
                 ref = got
             elif got != ref:
                 raise RuntimeError("tuning trial changed the result: %r vs %r" % (got, ref))
-            ts.append(r["enum_ms"])
+            ts.append(ms)
         t = float(np.median(ts))
         trials.append(dict(knobs, enum_ms=t, samples=ts))
         if log:
@@ -126,7 +133,8 @@ def tune(g, rank: str = "degree", sched: str = "degree", cost=None, grid=GRID, s
         return time_limit_s is not None and time.perf_counter() - t_start > time_limit_s
 
     # warm the workspace (and size the handoff arena) with the defaults
-    mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(DEFAULT))
+    if trial is None:
+        mce_static(dg, rank=rank, sched=sched, cost=cost, **launch_kwargs(DEFAULT))
     best, best_t = None, float("inf")
     points = [dict(DEFAULT)]
     for name, values in grid:

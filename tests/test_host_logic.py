@@ -138,3 +138,38 @@ def test_size_distribution_summary():
     s = D.size_distribution(h)
     assert s["bins"] == {2: 6, 3: 3, 7: 1} and s["cliques"] == 10 and s["largest"] == 7
     assert abs(s["mean"] - (12 + 9 + 7) / 10) < 1e-12
+
+
+def test_tuner_search_and_near_tie_rule():
+    # the grid, the coordinate search and the rule that gives near-ties (within
+    # NEAR) to the by-subproblem compact order, on a synthetic timing table
+    from paper_2001_11433_amd import tuner
+
+    def fake(knobs):
+        t = 100.0
+        t -= 10.0 if knobs["compact"] == 28 else 0.0
+        t -= 5.0 if knobs["waves_per_cu"] == 4 else 0.0
+        t -= 1.0 if knobs["donate_interval"] == 4096 else 0.0
+        t -= {0: 0.0, 1: 3.0, 2: 2.5}[knobs.get("compact_order", 0)]
+        return t, (7, 11, 13)
+
+    r = tuner.tune(None, trial=fake, path=None, samples=1)
+    best = r["best"]
+    assert (best["compact"], best["waves_per_cu"], best["donate_interval"]) == (28, 4, 4096)
+    # order 1 is fastest (81.0 ms) but order 2 (81.5 ms) is within 1.5 %: order 2 wins
+    assert best["compact_order"] == 2 and r["enum_ms"] == 81.5
+    assert min(t["enum_ms"] for t in r["trials"]) == 81.0
+
+    # outside the tie band the fastest setting stays
+    def fake2(knobs):
+        t, res = fake(knobs)
+        return (t + 2.0 if knobs.get("compact_order") == 2 else t), res
+
+    assert tuner.tune(None, trial=fake2, path=None, samples=1)["best"]["compact_order"] == 1
+
+
+def test_tuner_refuses_a_setting_that_changes_the_result():
+    import pytest
+    from paper_2001_11433_amd import tuner
+    with pytest.raises(RuntimeError):
+        tuner.tune(None, trial=lambda k: (1.0, (1, 2, 3 + (k["waves_per_cu"] == 16))), path=None, samples=1)
