@@ -445,7 +445,7 @@ int orc_csr_valid(uint64_t n, const uint64_t* rp, const uint32_t* col) { return 
 int orc_rank_metric(uint64_t n, const uint64_t* rp, const uint32_t* col, int kind, uint64_t* metric) {
   Adj A = adj_from_csr(n, rp, col);
   std::vector<uint64_t> m = metric_of(A, kind);
-  std::memcpy(metric, m.data(), n * sizeof(uint64_t));
+  if (n) std::memcpy(metric, m.data(), n * sizeof(uint64_t));  // an empty graph has no metric (and m.data() may be null)
   return 0;
 }
 
