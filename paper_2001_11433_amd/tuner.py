@@ -193,26 +193,32 @@ def lookup_imce(g, path: str = TABLE, family: Optional[str] = None) -> dict:
 
 
 def tune_imce(g, batches, start: Optional[dict] = None, space=IMCE_SPACE, path: Optional[str] = TABLE,
-              key: Optional[str] = None, log=None) -> dict:
+              key: Optional[str] = None, log=None, trial=None) -> dict:
     """Coordinate search of the launch knobs of the incremental step by the
     mean device time of `batches` (each trial replays them on a fresh state,
     after one untimed batch); every trial must report the same batch
-    results.  Recorded under `key` (default: the graph signature + "-imce")."""
-    import torch
+    results.  Recorded under `key` (default: the graph signature + "-imce").
+    `trial(knobs) -> (per-batch results, per-batch ms)` stands in for the
+    device replay (the search itself is then testable without a GPU)."""
     trials = []
     ref = None
 
-    def run(knobs):
-        nonlocal ref
+    def replay(knobs):
+        import torch
         st = ImceState(g, **launch_kwargs(knobs))
         out, ms = [], []
-        for i, (a, b) in enumerate(batches):
+        for a, b in batches:
             torch.cuda.synchronize()
             r = st.add(a, b)
             out.append((r["n_new"], r["n_del"], r["hash_new"], r["hash_del"]))
-            if i:
-                ms.append(r["ms"])
+            ms.append(r["ms"])
         st.close()
+        return out, ms
+
+    def run(knobs):
+        nonlocal ref
+        out, ms = (trial or replay)(knobs)
+        ms = ms[1:]  # the first batch is untimed
         if ref is None:
             ref = out
         elif out != ref:

@@ -1,6 +1,8 @@
-"""Host-side logic that needs no GPU: latency percentiles, tuner keys."""
+"""Host-side logic that needs no GPU: latency percentiles, tuner keys and
+search, admission, the bench's ties to the profiles, diagnostics."""
 
 import numpy as np
+import pytest
 
 import graphgen as gg
 
@@ -169,7 +171,22 @@ def test_tuner_search_and_near_tie_rule():
 
 
 def test_tuner_refuses_a_setting_that_changes_the_result():
-    import pytest
     from paper_2001_11433_amd import tuner
     with pytest.raises(RuntimeError):
         tuner.tune(None, trial=lambda k: (1.0, (1, 2, 3 + (k["waves_per_cu"] == 16))), path=None, samples=1)
+
+
+def test_incremental_tuner_search():
+    # coordinate search over the incremental step's knobs on a synthetic
+    # timing table; the first batch of each replay is not timed
+    from paper_2001_11433_amd import tuner
+
+    def fake(knobs):
+        t = 10.0 - (2.0 if knobs["donate_interval"] == 64 else 0.0) - (1.0 if knobs["waves_per_cu"] == 2 else 0.0)
+        return [(1, 2, 3, 4)] * 3, [99.0, t, t]
+
+    r = tuner.tune_imce(None, [None] * 3, trial=fake, path=None)
+    assert (r["best"]["donate_interval"], r["best"]["waves_per_cu"], r["mean_ms"]) == (64, 2, 7.0)
+    with pytest.raises(RuntimeError):
+        tuner.tune_imce(None, [None] * 3, path=None,
+                        trial=lambda k: ([(1, 2, 3, 4 + (k["compact"] == "inline"))] * 3, [1.0] * 3))
